@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark: SHA3-256 over 2^24 messages of 64 bytes on one MI355X.
+
+One step = one keccak_batch call over the whole resident batch (the full
+hot path: block counts, bucketing decision, scheduling and the persistent
+hashing kernel).  W untimed warmup steps, then exactly K timed steps between
+two device synchronisations.  Prints one JSON line with Mhash/s, GB/s hashed,
+the plain one-launch form on the same inputs, the roofline of the dominant
+kernel (timed live with HIP events on its launch stream) and the CPU oracle
+timed on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SHA3-256 Mhash/s (64 B msgs) + GB/s hashed; batched vs plain, bit-exact"
+N_MSGS = 1 << 24
+MSG_BYTES = 64
+SEED = 2
+VARIANT = 1  # SHA3-256
+
+# 32-bit VALU operations per Keccak-f[1600] on gfx950 with 3-input logic ops
+# (v_bitop3): per round theta 20 + 10 + 50, rho 48, chi 50 = 178; iota xors
+# 24 low halves and 13 high halves of the round constants over the 24 rounds.
+OPS_PER_PERMUTATION = 24 * 178 + 37
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one 32-bit op per lane-cycle
+PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_persistent_sha3_256_2p24x64.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1902_05320_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(src_hash: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the kernel source as it is now."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != src_hash:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(batch, target_s: float = 10.0) -> dict:
+    """The lane-level C oracle, as it stands, on a bounded prefix of the batch."""
+    from oracle import o2
+    threads = o2.default_threads()
+    cal = 1 << 14
+    t0 = time.perf_counter()
+    o2.sha3_batch(256, batch.data, batch.offsets[:cal], batch.lengths[:cal], threads=threads)
+    rate = cal / max(time.perf_counter() - t0, 1e-6)
+    sample = int(min(batch.n, max(cal, rate * target_s)))
+    t0 = time.perf_counter()
+    o2.sha3_batch(256, batch.data, batch.offsets[:sample], batch.lengths[:sample], threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(sample / dt / 1e6, 4), "unit": "Mhash/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {sample} of the {batch.n} 64-byte messages (SHA3-256), "
+                      f"lane-level C oracle on {threads} host threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (for counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the batch would shard across GPUs with no exchange, see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1902_05320_amd import kbatch, workloads
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+        return
+
+    print(f"[bench] generating {N_MSGS} x {MSG_BYTES} B (seed {SEED})", file=sys.stderr, flush=True)
+    batch = workloads.uniform(N_MSGS, MSG_BYTES, seed=SEED, variant=VARIANT)
+    data = torch.from_numpy(batch.data).to(dev)
+    offs = torch.from_numpy(batch.offsets).to(dev)
+    lens = torch.from_numpy(batch.lengths).to(dev)
+    out = torch.empty((N_MSGS, 32), dtype=torch.uint8, device=dev)
+    kbatch.reserve(N_MSGS)
+
+    def step(mode="persistent"):
+        kbatch.keccak_batch(VARIANT, data, offs, lens, out=out, mode=mode, check_bounds=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    kbatch.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, k_launches = kbatch.timing_read()
+    kbatch.timing_enable(False)
+    ms_per_step = 1e3 * wall / args.steps
+    mhash = N_MSGS * args.steps / wall / 1e6
+    gbps = N_MSGS * MSG_BYTES * args.steps / wall / 1e9
+    print(f"[bench] persistent: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # bit-exact spot check of the timed output against the oracle (untimed)
+    from oracle import o2
+    rng = np.random.Generator(np.random.PCG64(7))
+    idx = np.unique(rng.integers(0, N_MSGS, 4096))
+    got = out.cpu().numpy()[idx]
+    want = o2.sha3_batch(256, batch.data, batch.offsets[idx], batch.lengths[idx])
+    bit_exact = bool((got == want).all())
+
+    plain = None
+    if not args.no_plain:
+        for _ in range(2):
+            step("plain")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step("plain")
+        torch.cuda.synchronize()
+        pw = time.perf_counter() - t0
+        plain = {"mhash_s": round(N_MSGS * args.steps / pw / 1e6, 2),
+                 "ms_per_step": round(1e3 * pw / args.steps, 4)}
+
+    avg_kernel_s = (k_ms / 1e3) / max(k_launches, 1)
+    achieved = N_MSGS * OPS_PER_PERMUTATION / avg_kernel_s / 1e12
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(src_hash)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
+                "traffic": traffic, "kernel": "k_persistent<SHA3-256>",
+                "kernel_ms": round(avg_kernel_s * 1e3, 4),
+                "ops_per_unit": OPS_PER_PERMUTATION, "unit_of_work": "message (1 permutation)"}
+
+    result = {
+        "metric": METRIC, "value": round(mhash, 2), "unit": "Mhash/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "sha3_256_uniform_2^24x64B", "n_msgs": N_MSGS,
+                   "msg_bytes": MSG_BYTES, "variant": "sha3_256", "seed": SEED,
+                   "form": "persistent", "resident_in_hbm": True},
+        "gb_per_s_hashed": round(gbps, 2),
+        "plain": plain,
+        "bit_exact_sample": bit_exact,
+        "roofline": roofline,
+        "kernel_source_hash": src_hash,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(batch)
+    print(json.dumps(result), flush=True)
+    if not bit_exact:
+        sys.exit(3)
+
+
+if __name__ == "__main__":
+    main()

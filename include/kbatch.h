@@ -1,0 +1,145 @@
+/*
+ * kbatch -- batch-mode SHA-3 on AMD MI355X (gfx950).
+ *
+ * C ABI of libkbatch.so.  Batch mode (Section 4 of "GPU Accelerated Keccak
+ * (SHA3) Algorithm"): many independent messages, each hashed on its own with
+ * SHA3-224/256/384/512 (Section 3.3, eqs. 13-16: Keccak[c = 2d] over
+ * M || 01 with pad10*1, eq. 11, and Keccak-f[1600], Section 3.1), one digest
+ * per message.  Tree mode (Section 4): merkle_root().
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named d_* are device memory owned by the caller (for example
+ *     a torch tensor's data_ptr()); the library never frees them.
+ *   - Work is enqueued on `stream` (NULL = the default stream) and the call
+ *     returns without waiting for it.  Inputs must stay valid and unchanged,
+ *     and outputs untouched, until the stream reaches that point.
+ *   - Messages are byte strings.  Message i is the d_lengths[i] bytes at
+ *     d_data + d_offsets[i]; offsets may be unaligned and slices may
+ *     overlap; length 0 is valid.  offsets[i] + lengths[i] must not exceed
+ *     the d_data allocation: the library cannot check that on the host (the
+ *     Python binding does).  d_offsets and d_lengths must be 8-byte aligned,
+ *     d_digests 4-byte aligned, and digests must not alias any input.
+ *   - n == 0 is a no-op returning KB_OK; NULL pointers are then allowed.
+ *   - On error nothing is enqueued, the call returns a KB_E* code and
+ *     keccak_last_error() (per host thread) describes it.
+ *   - The library owns per-(device, stream) workspace that grows on demand;
+ *     growing it waits for the device.  keccak_reserve() sizes it up front,
+ *     keccak_release() frees it.  Calls on one stream are ordered; calls on
+ *     different streams use different workspaces and may run concurrently.
+ */
+#ifndef KBATCH_H
+#define KBATCH_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* SHA-3 variants (Section 3.3): digest d bits, capacity c = 2d, rate
+ * r = 1600 - c.  Digest/rate in bytes: 28/144, 32/136, 48/104, 64/72. */
+enum kb_variant { KB_SHA3_224 = 0, KB_SHA3_256 = 1, KB_SHA3_384 = 2, KB_SHA3_512 = 3 };
+
+enum kb_status {
+  KB_OK = 0,
+  KB_EINVAL = -1, /* bad argument: variant, NULL pointer with n > 0, alignment, leaf_size 0 */
+  KB_ENOMEM = -2, /* workspace could not be allocated */
+  KB_EHIP = -3    /* a HIP runtime call or kernel launch failed */
+};
+
+/* Scheduling forms of a batch (all give identical digests). */
+enum kb_mode {
+  KB_MODE_PERSISTENT = 0, /* bucket by block count, longest first, one persistent launch */
+  KB_MODE_PLAIN = 1,      /* one thread per message in arrival order, one launch (the
+                             paper's "one thread per message", Section 4.1) */
+  KB_MODE_PER_BUCKET = 2  /* bucket by block count, one plain launch per bucket (waits on
+                             the host for the bucket sizes) */
+};
+
+/* Tuning knobs of the persistent form; a zero field means "library default". */
+typedef struct kb_tile {
+  int32_t block_threads;    /* threads per workgroup: 64, 128 or 256 */
+  int32_t waves_per_simd;   /* persistent grid: resident waves per SIMD (1..8) */
+  int32_t steps_per_item;   /* wave-blocks of work per queue item (>= 1) */
+  int32_t reserved;
+} kb_tile;
+
+/*
+ * keccak_batch -- SHA3-{224,256,384,512} of n messages (batch mode, Section
+ * 4; the sponge of Section 3.2 over Keccak-f[1600] of Section 3.1).
+ *   variant    kb_variant.
+ *   d_data     message bytes.
+ *   d_offsets  uint64[n] byte offsets into d_data.
+ *   d_lengths  uint64[n] byte lengths.
+ *   n          number of messages (< 2^32).
+ *   d_digests  uint8[n * D] output, digest i at i * D (D = digest bytes).
+ * Uses the persistent, length-bucketed form (KB_MODE_PERSISTENT).
+ */
+int keccak_batch(int variant, const uint8_t* d_data, const uint64_t* d_offsets,
+                 const uint64_t* d_lengths, uint64_t n, uint8_t* d_digests, hipStream_t stream);
+
+/*
+ * keccak_batch_mixed -- like keccak_batch with a variant per message.
+ *   d_variants  uint8[n], each 0..3 (kb_variant).
+ *   d_digests   uint8[n * 64]; slot i holds digest i followed by zeros.  A
+ *               slot whose variant byte is out of range is all zeros.
+ */
+int keccak_batch_mixed(const uint8_t* d_variants, const uint8_t* d_data,
+                       const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n,
+                       uint8_t* d_digests, hipStream_t stream);
+
+/*
+ * keccak_batch_ex -- either form above with an explicit scheduling mode and
+ * tile (tile may be NULL).  variant = -1 selects the mixed form (d_variants
+ * required, 64-byte output slots); otherwise d_variants is ignored.
+ */
+int keccak_batch_ex(int variant, const uint8_t* d_variants, const uint8_t* d_data,
+                    const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n,
+                    uint8_t* d_digests, int mode, const kb_tile* tile, hipStream_t stream);
+
+/*
+ * merkle_root -- tree mode (Section 4: messages hashed in twos up to one
+ * root).  The input is cut into n = max(1, ceil(total_len / leaf_size))
+ * leaves of leaf_size bytes (the last may be short; total_len 0 gives one
+ * empty leaf).  Leaf digest = H(leaf); a parent = H(left || right) over the
+ * two D-byte child digests; an unpaired last node at a level is carried up
+ * unchanged.  H is the SHA-3 `variant`.  The D-byte root is written to
+ * d_root (device memory).  leaf_size 0 is KB_EINVAL.
+ */
+int merkle_root(int variant, const uint8_t* d_data, uint64_t total_len, uint64_t leaf_size,
+                uint8_t* d_root, hipStream_t stream);
+
+/* Digest and rate sizes in bytes of a variant; -1 if it is out of range. */
+int keccak_digest_bytes(int variant);
+int keccak_rate_bytes(int variant);
+
+/* Pre-size the workspace of (current device, stream) for batches of up to
+ * max_msgs messages and trees of up to max_leaves leaves. */
+int keccak_reserve(uint64_t max_msgs, uint64_t max_leaves, hipStream_t stream);
+
+/* Free every workspace this process holds (waits for the devices). */
+int keccak_release(void);
+
+/* Measurement hook.  While enabled (on != 0) every hashing-kernel launch
+ * (persistent, plain, per-bucket and tree-level kernels) is bracketed by a
+ * pair of HIP events recorded on the stream it is launched on.  Enabling
+ * clears the record.  Not for use during graph capture. */
+int keccak_timing_enable(int on);
+
+/* Sum of the bracketed kernel durations in milliseconds and the number of
+ * bracketed launches since timing was enabled; waits for those events. */
+int keccak_timing_read(double* total_ms, uint64_t* launches);
+
+/* Text of the last error on the calling host thread ("" if none). */
+const char* keccak_last_error(void);
+
+/* Library version string. */
+const char* keccak_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBATCH_H */

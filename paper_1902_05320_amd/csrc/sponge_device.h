@@ -1,0 +1,144 @@
+// The SHA-3 sponge (Section 3.2, eqs. 11-16) for one message per thread.
+//
+// Each block of the padded message P = M || 01 || pad10*1 is staged through a
+// per-thread row of LDS before it is xored into the state:
+//   1. the 16-byte-aligned chunks that hold the block's bytes are read with
+//      global_load_dwordx4 and stored to the row unchanged, so a block at any
+//      byte offset costs at most ceil((R + 15) / 16) vector loads;
+//   2. on the final block the bytes past the message end are cleared and the
+//      suffix/padding bytes are written with byte-granular LDS stores: 0x06
+//      (bits 0,1 of the suffix "01" then the first pad bit) at the message
+//      end, 0x80 (the last pad bit) on byte R-1, or 0x86 when both fall on
+//      byte R-1 -- the byte form of N || pad10*1 with j = (-m-2) mod r;
+//   3. the row is read back as dwords and realigned with v_alignbyte.
+// The data-dependent byte positions thus cost LDS address arithmetic, not
+// per-dword VALU masking.
+//
+// Variant `V` is 0..3 (SHA3-224/256/384/512, rate fixed at compile time) or
+// kMixed (rate chosen per thread at run time).
+#pragma once
+
+#include "keccak_device.h"
+
+namespace kb {
+
+constexpr int kMixed = 4;
+
+template <int V>
+struct SpongeShape {
+  static constexpr int kMaxRate = V == kMixed ? 144 : rate_bytes_of(V);
+  static constexpr int kMaxRateDw = kMaxRate / 4;
+  // 16-byte chunks that can hold R bytes starting at any offset mod 16
+  static constexpr int kChunks = (kMaxRate + 15 + 15) / 16;
+  // chunk area plus room for the padding stores past the last chunk
+  static constexpr int kRowDw = kChunks * 4 + 4;
+  static constexpr int kMaxDigestDw = V == kMixed ? 16 : digest_bytes_of(V) / 4;
+};
+
+__device__ __forceinline__ int rate_bytes_rt(int v) { return 200 - 2 * (v == 0 ? 28 : v == 1 ? 32 : v == 2 ? 48 : 64); }
+__device__ __forceinline__ int digest_bytes_rt(int v) { return v == 0 ? 28 : v == 1 ? 32 : v == 2 ? 48 : 64; }
+
+// Stage one rate block of the padded message into `row` and return it as
+// little-endian dwords in w[0 .. kMaxRateDw).  `p` points at the block's
+// first message byte, `rem` is min(bytes left, R), `fin` marks the final
+// block (rem < R then).
+template <int V>
+__device__ __forceinline__ void stage_block(uint32_t* __restrict__ row, const uint8_t* p,
+                                            uint32_t rem, int R, bool fin,
+                                            uint32_t (&w)[SpongeShape<V>::kMaxRateDw]) {
+  using S = SpongeShape<V>;
+  const uint32_t s16 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p) & 15u);
+  // derive the aligned base by pointer arithmetic (not from an integer) so
+  // the loads stay in the global address space
+  const uint4* base = reinterpret_cast<const uint4*>(p - s16);
+  const uint32_t nv = s16 + rem;  // row bytes [s16, nv) hold message bytes
+  // issue every chunk load before the first LDS store
+  uint4 c[S::kChunks];
+#pragma unroll
+  for (int j = 0; j < S::kChunks; ++j) {
+    c[j] = make_uint4(0u, 0u, 0u, 0u);
+    // only chunks holding at least one message byte are read
+    if (rem != 0u && 16u * j < nv) c[j] = base[j];
+  }
+  uint4* row4 = reinterpret_cast<uint4*>(row);
+#pragma unroll
+  for (int j = 0; j < S::kChunks; ++j) row4[j] = c[j];
+  if (fin) {
+    // clear the tail of the last chunk: up to three whole dwords past the
+    // dword holding byte nv, then bytes nv..nv+2 (suffix byte first)
+    const uint32_t d0 = (nv + 3u) >> 2;
+    row[d0] = 0u;
+    row[d0 + 1] = 0u;
+    row[d0 + 2] = 0u;
+    uint8_t* rb = reinterpret_cast<uint8_t*>(row);
+    rb[nv] = 0x06u;
+    rb[nv + 1] = 0u;
+    rb[nv + 2] = 0u;
+    rb[s16 + R - 1] = rem + 1u == static_cast<uint32_t>(R) ? 0x86u : 0x80u;
+  }
+  const uint32_t* src = row + (s16 >> 2);
+  const uint32_t sh = s16 & 3u;
+#pragma unroll
+  for (int k = 0; k < S::kMaxRateDw; ++k) w[k] = __builtin_amdgcn_alignbyte(src[k + 1], src[k], sh);
+}
+
+// Absorb the whole message and run the permutation on every block; on return
+// A holds Keccak-f[1600] of the last absorbed state, i.e. the squeezed output
+// lanes (d <= r for every SHA-3 variant, so one squeeze suffices).
+template <int V>
+__device__ __forceinline__ void sponge_hash(Lane (&A)[25], const uint8_t* msg, uint64_t len,
+                                            int var, uint32_t* __restrict__ row) {
+  using S = SpongeShape<V>;
+  const int R = V == kMixed ? rate_bytes_rt(var) : rate_bytes_of(V);
+  const int RW = R / 4;
+  // blocks of the padded message: the 2 suffix bits and the pad fit after
+  // any byte-aligned message, so nb = floor(L / R) + 1
+  const uint64_t nb = len / static_cast<uint64_t>(R) + 1u;
+  for (uint64_t b = 0; b < nb; ++b) {
+    const bool fin = b + 1u == nb;
+    const uint8_t* p = msg + b * static_cast<uint64_t>(R);
+    const uint32_t rem = fin ? static_cast<uint32_t>(len - b * static_cast<uint64_t>(R))
+                             : static_cast<uint32_t>(R);
+    uint32_t w[S::kMaxRateDw];
+    stage_block<V>(row, p, rem, R, fin, w);
+    if (b == 0) {
+#pragma unroll
+      for (int k = 0; k < 50; ++k) {
+        const uint32_t v = (k < S::kMaxRateDw && k < RW) ? w[k < S::kMaxRateDw ? k : 0] : 0u;
+        if (k & 1)
+          A[k >> 1].hi = v;
+        else
+          A[k >> 1].lo = v;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < S::kMaxRateDw; ++k) {
+        const uint32_t v = k < RW ? w[k] : 0u;
+        if (k & 1)
+          A[k >> 1].hi ^= v;
+        else
+          A[k >> 1].lo ^= v;
+      }
+    }
+    keccak_rounds_0_22(A);
+    if (!fin) keccak_round(A, 23);
+  }
+  keccak_round(A, 23);
+}
+
+// Trunc_d of the squeezed state: the first D bytes are dwords 0..D/4-1 in
+// lane order (lo, hi).  `out` must be 4-byte aligned.  In the mixed form every
+// slot is 64 bytes, zero past the digest.
+template <int V>
+__device__ __forceinline__ void store_digest(uint8_t* out, const Lane (&A)[25], int var) {
+  using S = SpongeShape<V>;
+  uint32_t* o = reinterpret_cast<uint32_t*>(out);
+  const int DW = V == kMixed ? digest_bytes_rt(var) / 4 : digest_bytes_of(V) / 4;
+#pragma unroll
+  for (int k = 0; k < S::kMaxDigestDw; ++k) {
+    const uint32_t v = (k & 1) ? A[k >> 1].hi : A[k >> 1].lo;
+    o[k] = k < DW ? v : 0u;
+  }
+}
+
+}  // namespace kb

@@ -1,0 +1,249 @@
+"""ctypes binding of libkbatch.so (argument marshalling only).
+
+Every step of the hashing path runs in the HIP library; this module checks
+arguments, takes device pointers from torch tensors and the HIP stream from
+torch, and calls the C ABI declared in include/kbatch.h.  There is no CPU
+fallback: if the library is not built or no GPU is present the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first so the library binds to the HIP runtime torch uses
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkbatch.so")
+
+SHA3_224, SHA3_256, SHA3_384, SHA3_512 = 0, 1, 2, 3
+VARIANTS = {"sha3_224": 0, "sha3_256": 1, "sha3_384": 2, "sha3_512": 3}
+DIGEST_BYTES = (28, 32, 48, 64)
+RATE_BYTES = (144, 136, 104, 72)
+
+MODE_PERSISTENT, MODE_PLAIN, MODE_PER_BUCKET = 0, 1, 2
+MODES = {"persistent": 0, "plain": 1, "per_bucket": 2}
+
+KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
+
+# the C ABI entry points, in include/kbatch.h order
+EXPORTS = (
+    "keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
+    "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
+    "keccak_timing_enable", "keccak_timing_read", "keccak_last_error", "keccak_version",
+)
+
+
+class KbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"kbatch error {code}: {msg}")
+        self.code = code
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("steps_per_item", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkbatch.so (no GPU needed) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_1902_05320_amd.build` "
+                           "or __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    lib.keccak_batch.argtypes = [i32, vp, vp, vp, u64, vp, vp]
+    lib.keccak_batch_mixed.argtypes = [vp, vp, vp, vp, u64, vp, vp]
+    lib.keccak_batch_ex.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile), vp]
+    lib.merkle_root.argtypes = [i32, vp, u64, u64, vp, vp]
+    lib.keccak_digest_bytes.argtypes = [i32]
+    lib.keccak_rate_bytes.argtypes = [i32]
+    lib.keccak_reserve.argtypes = [u64, u64, vp]
+    lib.keccak_release.argtypes = []
+    lib.keccak_timing_enable.argtypes = [i32]
+    lib.keccak_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_uint64)]
+    lib.keccak_last_error.argtypes = []
+    lib.keccak_last_error.restype = ctypes.c_char_p
+    lib.keccak_version.argtypes = []
+    lib.keccak_version.restype = ctypes.c_char_p
+    for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
+              "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
+              "keccak_timing_enable", "keccak_timing_read"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("kbatch needs a ROCm GPU; none is visible")
+
+
+def _check(rc: int):
+    if rc != KB_OK:
+        msg = load_library().keccak_last_error().decode(errors="replace")
+        raise KbError(rc, msg)
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+
+def _as_u64_view(t: torch.Tensor, name: str, n: int | None = None) -> torch.Tensor:
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"{name} must be int64/uint64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    t = t.contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return t
+
+
+def variant_id(variant) -> int:
+    if isinstance(variant, str):
+        return VARIANTS[variant]
+    v = int(variant)
+    if v not in (0, 1, 2, 3):
+        raise ValueError(f"variant {variant!r} is not a SHA-3 variant")
+    return v
+
+
+def _check_bounds(data: torch.Tensor, offsets: torch.Tensor, lengths: torch.Tensor):
+    """Every slice must lie inside `data` (the C ABI cannot check this)."""
+    if offsets.numel() == 0:
+        return
+    if bool((offsets < 0).any()) or bool((lengths < 0).any()):
+        raise ValueError("offsets and lengths must be non-negative")
+    end = int((offsets + lengths).max())
+    if end > data.numel():
+        raise ValueError(f"a message ends at byte {end}, past the data ({data.numel()} bytes)")
+
+
+def keccak_batch(variant, data: torch.Tensor, offsets: torch.Tensor, lengths: torch.Tensor,
+                 out: torch.Tensor | None = None, stream=None, mode="persistent",
+                 tile: Tile | None = None, check_bounds: bool = True) -> torch.Tensor:
+    """SHA-3 digests of every (offset, length) slice of `data`; returns
+    uint8[n, D] on the device.  `mode` is persistent, plain or per_bucket."""
+    _require_gpu()
+    lib = load_library()
+    v = variant_id(variant)
+    n = offsets.numel()
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    data = data.contiguous()
+    offsets = _as_u64_view(offsets, "offsets")
+    lengths = _as_u64_view(lengths, "lengths", n)
+    if check_bounds:
+        _check_bounds(data, offsets, lengths)
+    D = DIGEST_BYTES[v]
+    if out is None:
+        out = torch.empty((n, D), dtype=torch.uint8, device=data.device)
+    elif out.dtype != torch.uint8 or out.numel() != n * D or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous uint8 tensor of {n * D} bytes")
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    if n == 0:
+        return out
+    dptr = _ptr(data) if data.numel() else ctypes.c_void_p(out.data_ptr())
+    if m == MODE_PERSISTENT and tile is None:
+        rc = lib.keccak_batch(v, dptr, _ptr(offsets), _ptr(lengths), n, _ptr(out),
+                              _stream_handle(stream))
+    else:
+        rc = lib.keccak_batch_ex(v, None, dptr, _ptr(offsets), _ptr(lengths), n, _ptr(out), m,
+                                 ctypes.byref(tile) if tile is not None else None,
+                                 _stream_handle(stream))
+    _check(rc)
+    return out
+
+
+def keccak_batch_mixed(variants: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor,
+                       lengths: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                       mode="persistent", tile: Tile | None = None,
+                       check_bounds: bool = True) -> torch.Tensor:
+    """Per-message variant (uint8 0..3); returns uint8[n, 64], zero past each digest."""
+    _require_gpu()
+    lib = load_library()
+    n = offsets.numel()
+    if variants.dtype != torch.uint8 or variants.numel() != n or not variants.is_cuda:
+        raise TypeError("variants must be a uint8 device tensor with one entry per message")
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    data = data.contiguous()
+    variants = variants.contiguous()
+    offsets = _as_u64_view(offsets, "offsets")
+    lengths = _as_u64_view(lengths, "lengths", n)
+    if check_bounds:
+        _check_bounds(data, offsets, lengths)
+    if out is None:
+        out = torch.empty((n, 64), dtype=torch.uint8, device=data.device)
+    elif out.dtype != torch.uint8 or out.numel() != n * 64 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous uint8 tensor of {n * 64} bytes")
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    if n == 0:
+        return out
+    dptr = _ptr(data) if data.numel() else ctypes.c_void_p(out.data_ptr())
+    if m == MODE_PERSISTENT and tile is None:
+        rc = lib.keccak_batch_mixed(_ptr(variants), dptr, _ptr(offsets), _ptr(lengths), n,
+                                    _ptr(out), _stream_handle(stream))
+    else:
+        rc = lib.keccak_batch_ex(-1, _ptr(variants), dptr, _ptr(offsets), _ptr(lengths), n,
+                                 _ptr(out), m, ctypes.byref(tile) if tile is not None else None,
+                                 _stream_handle(stream))
+    _check(rc)
+    return out
+
+
+def merkle_root(variant, data: torch.Tensor, leaf_size: int, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """Root of the binary hash tree over leaf_size-byte leaves (uint8[D])."""
+    _require_gpu()
+    lib = load_library()
+    v = variant_id(variant)
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    if leaf_size <= 0:
+        raise ValueError("leaf_size must be positive")
+    data = data.contiguous()
+    D = DIGEST_BYTES[v]
+    if out is None:
+        out = torch.empty(D, dtype=torch.uint8, device=data.device)
+    rc = lib.merkle_root(v, _ptr(data), data.numel(), int(leaf_size), _ptr(out),
+                         _stream_handle(stream))
+    _check(rc)
+    return out
+
+
+def reserve(max_msgs: int, max_leaves: int = 0, stream=None):
+    _check(load_library().keccak_reserve(int(max_msgs), int(max_leaves), _stream_handle(stream)))
+
+
+def release():
+    _check(load_library().keccak_release())
+
+
+def timing_enable(on: bool = True):
+    """Bracket every hashing-kernel launch with HIP events on its stream."""
+    _check(load_library().keccak_timing_enable(1 if on else 0))
+
+
+def timing_read() -> tuple[float, int]:
+    """(total kernel milliseconds, launches) since timing_enable()."""
+    ms, cnt = ctypes.c_double(0.0), ctypes.c_uint64(0)
+    _check(load_library().keccak_timing_read(ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def version() -> str:
+    return load_library().keccak_version().decode()

@@ -1,0 +1,67 @@
+"""The C-ABI library loads without a GPU, exports every symbol the header
+declares, and rejects bad arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kbatch.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)
+    return [n for n in names if not n.startswith("_")]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1902_05320_amd import kbatch
+    if not os.path.exists(kbatch.LIB_PATH):
+        pytest.skip("libkbatch.so not built")
+    return kbatch.load_library()
+
+
+def test_header_declares_the_binding_exports():
+    from paper_1902_05320_amd import kbatch
+    assert sorted(_declared_functions()) == sorted(kbatch.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_sizes(lib):
+    assert [lib.keccak_digest_bytes(v) for v in range(4)] == [28, 32, 48, 64]
+    assert [lib.keccak_rate_bytes(v) for v in range(4)] == [144, 136, 104, 72]
+    assert lib.keccak_digest_bytes(4) == -1 and lib.keccak_rate_bytes(-1) == -1
+    assert lib.keccak_version().startswith(b"kbatch")
+
+
+def test_argument_errors_need_no_device(lib):
+    from paper_1902_05320_amd import kbatch as kb
+    p = ctypes.c_void_p(0x1000)
+    # unknown variant
+    assert lib.keccak_batch(7, p, p, p, 4, p, None) == kb.KB_EINVAL
+    assert b"variant" in lib.keccak_last_error()
+    # n == 0 is a no-op, NULLs allowed
+    assert lib.keccak_batch(1, None, None, None, 0, None, None) == kb.KB_OK
+    assert lib.keccak_last_error() == b""
+    # NULL with n > 0
+    assert lib.keccak_batch(1, p, None, p, 4, p, None) == kb.KB_EINVAL
+    assert lib.keccak_batch_mixed(None, p, p, p, 4, p, None) == kb.KB_EINVAL
+    # misaligned metadata / output
+    assert lib.keccak_batch(1, p, ctypes.c_void_p(0x1004), p, 4, p, None) == kb.KB_EINVAL
+    assert lib.keccak_batch(1, p, p, p, 4, ctypes.c_void_p(0x1002), None) == kb.KB_EINVAL
+    # unknown mode, bad mixed flag
+    assert lib.keccak_batch_ex(1, None, p, p, p, 4, p, 9, None, None) == kb.KB_EINVAL
+    assert lib.keccak_batch_ex(-2, None, p, p, p, 4, p, 0, None, None) == kb.KB_EINVAL
+    # tree mode
+    assert lib.merkle_root(1, p, 100, 0, p, None) == kb.KB_EINVAL
+    assert lib.merkle_root(5, p, 100, 10, p, None) == kb.KB_EINVAL
+    assert lib.merkle_root(1, p, 100, 10, None, None) == kb.KB_EINVAL

@@ -1,0 +1,229 @@
+"""GPU parity: every digest from the HIP library equals the CPU oracle's,
+byte for byte, on seeded inputs.  Needs an MI355X; run with -m gpu."""
+
+import numpy as np
+import pytest
+
+from paper_1902_05320_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+RATES = (144, 136, 104, 72)
+DIGEST = (28, 32, 48, 64)
+MODES = ("persistent", "plain", "per_bucket")
+
+
+@pytest.fixture(scope="module")
+def kb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_05320_amd import kbatch
+    kbatch.load_library()
+    return kbatch
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _to_dev(batch):
+    import torch
+    data = torch.from_numpy(batch.data).cuda() if batch.data.size else torch.zeros(1, dtype=torch.uint8, device="cuda")
+    offs = torch.from_numpy(batch.offsets.astype(np.int64)).cuda()
+    lens = torch.from_numpy(batch.lengths.astype(np.int64)).cuda()
+    var = torch.from_numpy(batch.variants.astype(np.uint8)).cuda()
+    return data, offs, lens, var
+
+
+def _gpu_batch(kb, v, batch, mode="persistent"):
+    import torch
+    data, offs, lens, _ = _to_dev(batch)
+    out = kb.keccak_batch(v, data, offs, lens, mode=mode)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _gpu_mixed(kb, batch, mode="persistent"):
+    import torch
+    data, offs, lens, var = _to_dev(batch)
+    out = kb.keccak_batch_mixed(var, data, offs, lens, mode=mode)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _mismatches(got, want):
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    return bad[:10].tolist(), bad.size
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_uniform_4096x64_sha3_256(kb, o2, mode):
+    b = wl.uniform(4096, 64, seed=1)
+    _say("uniform 4096x64B sha3_256", mode)
+    got = _gpu_batch(kb, 1, b, mode)
+    want = o2.sha3_batch(256, b.data, b.offsets, b.lengths)
+    assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
+
+
+@pytest.mark.parametrize("v", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", MODES)
+def test_every_length_to_3R_unaligned(kb, o2, v, mode):
+    # every length 0 .. 3R+1, packed with a 3-byte gap so offsets hit every
+    # residue mod 16; the first message starts at byte 5
+    R = RATES[v]
+    b = wl.explicit(np.arange(0, 3 * R + 2), seed=10 + v, variant=v, gap=3, lead=5)
+    _say("every length sha3 variant", v, mode)
+    got = _gpu_batch(kb, v, b, mode)
+    want = o2.sha3_batch(8 * DIGEST[v], b.data, b.offsets, b.lengths)
+    assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_uneven_mixed_small(kb, o2, mode):
+    # log-uniform lengths in [0, 16 KiB], variant per message; spans many
+    # workgroups and a ragged tail (n not a multiple of 64)
+    b = wl.uneven(20000 + 37, 16384, seed=3)
+    _say("uneven mixed n=20037", mode)
+    got = _gpu_mixed(kb, b, mode)
+    want = o2.sha3_batch_mixed(b.variants, b.data, b.offsets, b.lengths)
+    assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
+
+
+@pytest.mark.parametrize("v", [1, 3])
+def test_uneven_single_variant(kb, o2, v):
+    b = wl.uneven(5000, 70000, seed=20 + v, variant=v)
+    _say("uneven single variant", v)
+    got = _gpu_batch(kb, v, b)
+    want = o2.sha3_batch(8 * DIGEST[v], b.data, b.offsets, b.lengths)
+    assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
+
+
+def test_mixed_invalid_variant_slot_is_zero(kb, o2):
+    b = wl.explicit([10, 200, 0, 77], seed=5, variant=np.array([1, 9, 3, 255], dtype=np.uint8))
+    _say("mixed invalid variant")
+    got = _gpu_mixed(kb, b)
+    assert not got[1].any() and not got[3].any()
+    want = o2.sha3_batch_mixed(np.array([1, 1, 3, 3], np.uint8), b.data, b.offsets, b.lengths)
+    assert (got[0] == want[0]).all() and (got[2] == want[2]).all()
+
+
+def test_edge_cases(kb, o2):
+    import torch
+    _say("edge: empty batch")
+    data = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    empty = torch.zeros(0, dtype=torch.int64, device="cuda")
+    out = kb.keccak_batch(1, data, empty, empty)
+    assert out.shape == (0, 32)
+    _say("edge: all-empty messages")
+    b = wl.explicit([0] * 300, seed=6)
+    got = _gpu_batch(kb, 1, b)
+    want = o2.sha3_batch(256, b.data, b.offsets, b.lengths)
+    assert (got == want).all()
+    _say("edge: one long message")
+    b = wl.explicit([1_000_003], seed=7, lead=9)
+    for v in range(4):
+        got = _gpu_batch(kb, v, b)
+        want = o2.sha3_batch(8 * DIGEST[v], b.data, b.offsets, b.lengths)
+        assert (got == want).all(), v
+    _say("edge: overlapping slices ending at the buffer end")
+    rng = np.random.Generator(np.random.PCG64(8))
+    n = 3000
+    buf = rng.integers(0, 256, 5000, dtype=np.uint8)
+    lens = rng.integers(0, 400, n)
+    offs = buf.size - lens - rng.integers(0, 3, n)  # most slices end within 2 bytes of the end
+    offs = np.maximum(offs, 0)
+    bt = wl.Batch(buf, offs.astype(np.int64), lens.astype(np.int64), np.ones(n, np.uint8), 8, "ov")
+    got = _gpu_batch(kb, 1, bt)
+    want = o2.sha3_batch(256, bt.data, bt.offsets, bt.lengths)
+    assert (got == want).all()
+
+
+def test_bounds_checked_in_binding(kb):
+    import torch
+    data = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    offs = torch.tensor([90], dtype=torch.int64, device="cuda")
+    lens = torch.tensor([11], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        kb.keccak_batch(1, data, offs, lens)
+    with pytest.raises(ValueError):
+        kb.merkle_root(1, data, 0)
+
+
+def test_order_and_repeat_invariance(kb):
+    import torch
+    b = wl.uneven(30000, 4000, seed=9)
+    data, offs, lens, var = _to_dev(b)
+    _say("repeat + permutation invariance")
+    a = kb.keccak_batch_mixed(var, data, offs, lens)
+    c = kb.keccak_batch_mixed(var, data, offs, lens)
+    perm = torch.randperm(b.n, generator=torch.Generator().manual_seed(1)).cuda()
+    p = kb.keccak_batch_mixed(var[perm].contiguous(), data, offs[perm].contiguous(),
+                              lens[perm].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+    assert torch.equal(p, a[perm])
+
+
+@pytest.mark.parametrize("v", [0, 1, 2, 3])
+def test_merkle_small_trees(kb, o2, v):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(40 + v))
+    for n_leaves in list(range(1, 18)) + [64, 65, 1000]:
+        for leaf in (1, 13, 4096):
+            total = n_leaves * leaf - (leaf // 3 if n_leaves > 1 else 0)
+            data = rng.integers(0, 256, max(total, 0), dtype=np.uint8)
+            _say("merkle", v, n_leaves, leaf, total)
+            d = torch.from_numpy(data).cuda() if total else torch.zeros(0, dtype=torch.uint8, device="cuda")
+            got = kb.merkle_root(v, d, leaf)
+            torch.cuda.synchronize()
+            assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], data, leaf)
+    _say("merkle empty input")
+    d = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    got = kb.merkle_root(v, d, 64)
+    torch.cuda.synchronize()
+    assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], np.zeros(0, np.uint8), 64)
+
+
+# --------------------------------------------------------------------------
+# Full-size workloads, in the launch configuration the benchmark times
+# --------------------------------------------------------------------------
+
+def test_full_uniform_2p24x64_sampled(kb, o2):
+    import torch
+    b = wl.uniform(1 << 24, 64, seed=2)
+    _say("full 2^24 x 64B sha3_256 persistent")
+    data, offs, lens, _ = _to_dev(b)
+    out = kb.keccak_batch(1, data, offs, lens)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(99))
+    idx = np.unique(np.concatenate([np.arange(4096), np.arange(b.n - 4096, b.n),
+                                    rng.integers(0, b.n, 1 << 16)]))
+    want = o2.sha3_batch(256, b.data, b.offsets[idx], b.lengths[idx])
+    assert _mismatches(got[idx], want)[1] == 0
+    del data, offs, lens, out
+
+
+def test_full_uneven_2p20_mixed(kb, o2):
+    import torch
+    b = wl.uneven(1 << 20, 16384, seed=3)
+    _say("full uneven 2^20 mixed persistent + plain")
+    data, offs, lens, var = _to_dev(b)
+    got = kb.keccak_batch_mixed(var, data, offs, lens)
+    plain = kb.keccak_batch_mixed(var, data, offs, lens, mode="plain")
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert (plain.cpu().numpy() == got).all()
+    want = o2.sha3_batch_mixed(b.variants, b.data, b.offsets, b.lengths)
+    assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
+
+
+def test_full_merkle_1gib(kb, o2):
+    import torch
+    data = wl.merkle(1 << 30, seed=5)
+    _say("full merkle 1 GiB / 4 KiB leaves")
+    d = torch.from_numpy(data).cuda()
+    got = kb.merkle_root(1, d, 4096)
+    torch.cuda.synchronize()
+    assert got.cpu().numpy().tobytes() == o2.merkle_root(256, data, 4096)
