@@ -81,6 +81,74 @@ def cpu_baseline(batch, target_s: float = 10.0) -> dict:
                       f"lane-level C oracle on {threads} host threads, {dt:.1f} s"}
 
 
+def time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_uneven(args, kbatch, workloads, torch, dev):
+    """2^20 messages, lengths log-uniform in [0, 16 KiB], variant per message:
+    persistent (bucketed) vs plain vs one launch per bucket."""
+    print("[bench] generating uneven 2^20 batch (seed 3)", file=sys.stderr, flush=True)
+    b = workloads.uneven(1 << 20, 16384, seed=3)
+    data = torch.from_numpy(b.data).to(dev)
+    offs = torch.from_numpy(b.offsets).to(dev)
+    lens = torch.from_numpy(b.lengths).to(dev)
+    var = torch.from_numpy(b.variants).to(dev)
+    out = torch.empty((b.n, 64), dtype=torch.uint8, device=dev)
+    rates = np.array([144, 136, 104, 72])[b.variants]
+    perms = int((b.lengths // rates + 1).sum())
+    res = {}
+    for mode in ("persistent", "plain", "per_bucket"):
+        fn = lambda: kbatch.keccak_batch_mixed(var, data, offs, lens, out=out, mode=mode,
+                                               check_bounds=False)
+        kbatch.timing_enable(True)
+        t = time_steps(torch, fn, args.steps, args.warmup)
+        k_ms, k_n = kbatch.timing_read()
+        kbatch.timing_enable(False)
+        steps_timed = args.steps + args.warmup
+        res[mode] = {"ms_per_step": round(t * 1e3, 4), "mhash_s": round(b.n / t / 1e6, 2),
+                     "gb_per_s_hashed": round(b.total_bytes / t / 1e9, 2),
+                     "kernel_ms_per_step": round(k_ms / steps_timed, 4),
+                     "kernel_frac_of_alu_peak": round(
+                         perms * OPS_PER_PERMUTATION / (k_ms / steps_timed * 1e-3) / 1e12
+                         / PEAK_INT32_TOPS, 4)}
+        print(f"[bench] uneven {mode}: {res[mode]}", file=sys.stderr, flush=True)
+    print(json.dumps({"config": {"workload": "uneven_mixed_2^20x[0,16KiB]", "seed": 3,
+                                 "total_bytes": b.total_bytes, "permutations": perms},
+                      "steps": args.steps, "warmup": args.warmup, **res}), flush=True)
+
+
+def bench_merkle(args, kbatch, workloads, torch, dev):
+    """1 GiB of seeded bytes in 4 KiB leaves, SHA3-256, up to one root."""
+    print("[bench] generating 1 GiB tree input (seed 5)", file=sys.stderr, flush=True)
+    total = 1 << 30
+    data = torch.from_numpy(workloads.merkle(total, seed=5)).to(dev)
+    root = torch.empty(32, dtype=torch.uint8, device=dev)
+    leaves = total // 4096
+    perms = leaves * (4096 // 136 + 1) + (leaves - 1)
+    kbatch.reserve(0, leaves)
+    kbatch.timing_enable(True)
+    t = time_steps(torch, lambda: kbatch.merkle_root(1, data, 4096, out=root), args.steps,
+                   args.warmup)
+    k_ms, k_n = kbatch.timing_read()
+    kbatch.timing_enable(False)
+    steps_timed = args.steps + args.warmup
+    print(json.dumps({"config": {"workload": "merkle_1GiB_4KiB_leaves_sha3_256", "seed": 5,
+                                 "leaves": leaves, "permutations": perms},
+                      "ms_per_root": round(t * 1e3, 4), "gb_per_s_hashed": round(total / t / 1e9, 2),
+                      "kernel_ms_per_root": round(k_ms / steps_timed, 4),
+                      "launches_per_root": k_n // steps_timed,
+                      "alu_frac_whole_root": round(perms * OPS_PER_PERMUTATION / t / 1e12
+                                                   / PEAK_INT32_TOPS, 4)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,7 +157,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a device-to-device copy of MIB MiB (for counter scaling)")
+                    help="only run the library's copy probe over MIB MiB (for counter scaling)")
+    ap.add_argument("--workload", default="uniform", choices=("uniform", "uneven", "merkle"),
+                    help="uniform: 2^24 x 64 B SHA3-256 (the reported metric); uneven: 2^20 "
+                         "mixed-variant messages, log-uniform lengths in [0, 16 KiB]; merkle: "
+                         "1 GiB in 4 KiB leaves")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,11 +182,14 @@ def main():
         nbytes = args.copy_calibration << 20
         a = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
         b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+        gbps = [kbatch.probe_copy(a, b) for _ in range(3)]
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 3,
+                          "gbps_read_plus_write": [round(g, 1) for g in gbps]}), flush=True)
         return
+    if args.workload == "uneven":
+        return bench_uneven(args, kbatch, workloads, torch, dev)
+    if args.workload == "merkle":
+        return bench_merkle(args, kbatch, workloads, torch, dev)
 
     print(f"[bench] generating {N_MSGS} x {MSG_BYTES} B (seed {SEED})", file=sys.stderr, flush=True)
     batch = workloads.uniform(N_MSGS, MSG_BYTES, seed=SEED, variant=VARIANT)
@@ -171,11 +246,13 @@ def main():
     achieved = N_MSGS * OPS_PER_PERMUTATION / avg_kernel_s / 1e12
     src_hash = kernel_source_hash()
     traffic = load_traffic(src_hash)
+    probe_tops, probe_mhz = kbatch.probe_valu()
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
                 "traffic": traffic, "kernel": "k_persistent<SHA3-256>",
-                "kernel_ms": round(avg_kernel_s * 1e3, 4),
-                "ops_per_unit": OPS_PER_PERMUTATION, "unit_of_work": "message (1 permutation)"}
+                "kernel_ms": round(avg_kernel_s * 1e3, 4), "launches_timed": k_launches,
+                "ops_per_unit": OPS_PER_PERMUTATION, "unit_of_work": "message (1 permutation)",
+                "probe_valu_tops": round(probe_tops, 2), "probe_sclk_mhz": round(probe_mhz, 0)}
 
     result = {
         "metric": METRIC, "value": round(mhash, 2), "unit": "Mhash/s", "n_gpus": 1,

@@ -132,6 +132,19 @@ int keccak_timing_enable(int on);
  * bracketed launches since timing was enabled; waits for those events. */
 int keccak_timing_read(double* total_ms, uint64_t* launches);
 
+/* Probe: sustained 32-bit VALU issue rate of the current device (tera
+ * lane-operations per second; a grid of 8 waves per SIMD running `iters`
+ * iterations of 16 independent 3-input xors per lane) and the shader clock
+ * seen by that kernel (MHz, from the shader and constant-rate counters).
+ * Synchronous; allocates 20 bytes of device memory for its duration. */
+int keccak_probe_valu(uint32_t iters, double* tops, double* sclk_mhz, hipStream_t stream);
+
+/* Probe: one device-to-device copy of `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned); *gbps = 2 * bytes / time (read + write).
+ * Synchronous.  Used to calibrate memory-traffic counters. */
+int keccak_probe_copy(const uint8_t* d_src, uint8_t* d_dst, uint64_t bytes, double* gbps,
+                      hipStream_t stream);
+
 /* Text of the last error on the calling host thread ("" if none). */
 const char* keccak_last_error(void);
 

@@ -30,7 +30,8 @@ KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
 EXPORTS = (
     "keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
     "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
-    "keccak_timing_enable", "keccak_timing_read", "keccak_last_error", "keccak_version",
+    "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_copy",
+    "keccak_last_error", "keccak_version",
 )
 
 
@@ -69,13 +70,17 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_timing_enable.argtypes = [i32]
     lib.keccak_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_uint64)]
+    lib.keccak_probe_valu.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), vp]
+    lib.keccak_probe_copy.argtypes = [vp, vp, u64, ctypes.POINTER(ctypes.c_double), vp]
     lib.keccak_last_error.argtypes = []
     lib.keccak_last_error.restype = ctypes.c_char_p
     lib.keccak_version.argtypes = []
     lib.keccak_version.restype = ctypes.c_char_p
     for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
-              "keccak_timing_enable", "keccak_timing_read"):
+              "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu",
+              "keccak_probe_copy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -243,6 +248,24 @@ def timing_read() -> tuple[float, int]:
     ms, cnt = ctypes.c_double(0.0), ctypes.c_uint64(0)
     _check(load_library().keccak_timing_read(ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def probe_valu(iters: int = 20000, stream=None) -> tuple[float, float]:
+    """(sustained int32 VALU tera-ops/s, shader clock MHz) of the current GPU."""
+    _require_gpu()
+    tops, mhz = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(load_library().keccak_probe_valu(int(iters), ctypes.byref(tops), ctypes.byref(mhz),
+                                            _stream_handle(stream)))
+    return tops.value, mhz.value
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> float:
+    """Device copy bandwidth (GB/s, read + write) of src -> dst."""
+    _require_gpu()
+    gbps = ctypes.c_double(0.0)
+    _check(load_library().keccak_probe_copy(_ptr(src), _ptr(dst), src.numel(), ctypes.byref(gbps),
+                                            _stream_handle(stream)))
+    return gbps.value
 
 
 def version() -> str:
