@@ -3,20 +3,30 @@
 // Pipeline of keccak_batch (persistent form), all enqueued on the caller's
 // stream with no host synchronisation:
 //   k_reset     clear histogram, cursors and control words
-//   k_count     block count nb = floor(L/R) + 1 per message, histogram of
-//               nb (bins 1..4094 exact, 4095 = "4095 or more"), and the cost
-//               of arrival order (sum over 64-message waves of 64 * max nb)
-//   k_plan      one workgroup: if arrival order wastes <= 2 % of the lane
-//               slots it is kept; otherwise bucket starts in descending nb
-//               (longest first).  Cuts the work into queue items of about
-//               `steps_per_item` permutations per lane.
+//   k_count     block count nb = floor(L/R) + 1 per message and its histogram
+//               (bins 1..4094 exact, 4095 = "4095 or more"); per 64-message
+//               wave of arrival order, the lane-slots a wave would idle
+//   k_plan      one workgroup: keep arrival order if it idles <= 2 % of the
+//               lane slots, else bucket starts in descending nb (longest
+//               first); queue-item counts per bucket (about `steps_per_item`
+//               permutations per lane each)
+//   k_items     one thread per queue item: its message range and bucket
 //   k_scatter   counting-sort scatter of message indices into `order`
 //               (skipped when arrival order is kept)
 //   k_persistent  a grid sized to the resident capacity pops items from an
-//               atomic counter; each lane hashes one message per step.
+//               atomic counter; each lane hashes one message per step.  The
+//               longest items run at raised wave priority so that the long
+//               absorb chains, which bound the makespan, are not slowed by
+//               round-robin issue with shorter work.
 // The plain form is one k_plain launch in arrival order; the per-bucket form
-// runs k_count/k_plan/k_scatter, reads the histogram back, and launches
+// runs the same scheduling kernels, reads the histogram back, and launches
 // k_plain once per non-empty bucket.
+//
+// Tree mode: k_tree hashes 256 leaves per workgroup and reduces them eight
+// levels in place (pairs of child digests, an unpaired last node carried up);
+// further k_tree launches reduce 256 nodes per workgroup until one is left.
+// Every level is written to its own region, so no workgroup reads a node
+// another one may overwrite.
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -44,17 +54,22 @@ constexpr int kScatterTile = 4096;  // messages per scatter workgroup
 
 // control words (uint32 indices into the ctl area)
 enum : int {
-  CTL_QUEUE = 0,     // persistent queue counter
-  CTL_NITEMS = 1,    // number of queue items
-  CTL_IDENTITY = 2,  // 1: arrival order kept, order[] unused
-  CTL_MAXKEY = 3,    // largest block-count key seen
-  CTL_SUM_NB = 4,    // uint64: sum of nb (words 4, 5)
-  CTL_SUM_WAVE = 6,  // uint64: sum over arrival-order waves of 64 * max nb (words 6, 7)
+  CTL_QUEUE = 0,       // persistent queue counter
+  CTL_NITEMS = 1,      // number of queue items
+  CTL_IDENTITY = 2,    // 1: arrival order kept, order[] unused
+  CTL_MAXKEY = 3,      // largest block-count key seen
+  CTL_USEFUL = 4,      // uint64: sum of (clamped) block counts (words 4, 5)
+  CTL_IDLE = 6,        // uint64: lane-slots arrival-order waves would idle (words 6, 7)
+  CTL_ID_PER = 8,      // arrival order: messages per queue item
+  CTL_PRIO_ITEMS = 9,  // items [0, PRIO_ITEMS) with key >= PRIO_KEY run at high priority
+  CTL_PRIO_KEY = 10,
   CTL_WORDS = 64
 };
 
 struct WorkItem {
   uint32_t begin, end;  // positions in order[] (message indices in arrival order)
+  uint32_t key;         // block-count bucket of the item (0 in arrival order)
+  uint32_t pad;
 };
 
 template <int V>
@@ -134,37 +149,80 @@ __global__ __launch_bounds__(kBlock) void k_persistent(
   uint32_t* row = lds + threadIdx.x * S::kRowDw;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t n_items = ctl[CTL_NITEMS];
+  const uint32_t prio_items = ctl[CTL_PRIO_ITEMS];
+  const uint32_t prio_key = ctl[CTL_PRIO_KEY];
   const uint32_t* ord = ctl[CTL_IDENTITY] ? nullptr : order;
   for (;;) {
     uint32_t t = 0;
     if (lane == 0)
       t = __hip_atomic_fetch_add(&ctl[CTL_QUEUE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    t = __shfl(t, 0);
+    t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
     if (t >= n_items) break;
     const WorkItem it = items[t];
+    if (t < prio_items && it.key >= prio_key)
+      __builtin_amdgcn_s_setprio(3);
+    else
+      __builtin_amdgcn_s_setprio(0);
     for (uint32_t pos = it.begin + lane; pos < it.end; pos += 64u) {
       const uint64_t i = ord ? ord[pos] : pos;
       hash_message<V>(data, offs, lens, vars, i, out, row);
     }
   }
+  __builtin_amdgcn_s_setprio(0);
 }
 
-// Strided messages for tree mode: message i is the min(msg_len, total - i *
-// stride) bytes at base + i * stride; its digest goes to out + i * D.
+// Tree mode.  Level l has m[l] nodes stored from byte offset off[l] of
+// `nodes` (level 0 = leaf digests).  Node j of level l+1 is H(node 2j ||
+// node 2j+1) of level l, or node 2j itself when it is the unpaired last one.
+struct TreeLevels {
+  uint64_t m[64];
+  uint64_t off[64];
+};
+
+// Workgroup w owns nodes [256 w, 256 w + 256) of level `first` and reduces
+// them `levels` levels.  first == 0: it also hashes those leaves (leaf i is
+// min(leaf_size, total - i * leaf_size) bytes at data + i * leaf_size).  Each
+// level is separated by a workgroup barrier, which also orders the global
+// node writes of one level before the reads of the next.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_strided(const uint8_t* __restrict__ base,
-                                                    uint64_t stride, uint64_t msg_len,
-                                                    uint64_t total, uint64_t count,
-                                                    uint8_t* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ data, uint64_t total,
+                                                 uint64_t leaf_size, uint8_t* __restrict__ nodes,
+                                                 int first, int levels, TreeLevels lv) {
   using S = SpongeShape<V>;
+  constexpr uint64_t D = kb::digest_bytes_of(V);
   __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
-  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= count) return;
-  const uint64_t off = i * stride;
-  const uint64_t len = total - off < msg_len ? total - off : msg_len;
-  Lane A[25];
-  kb::sponge_hash<V>(A, base + off, len, V, lds + threadIdx.x * S::kRowDw);
-  kb::store_digest<V>(out + i * static_cast<uint64_t>(kb::digest_bytes_of(V)), A, V);
+  uint32_t* row = lds + threadIdx.x * S::kRowDw;
+  const uint64_t w = blockIdx.x;
+  if (first == 0) {
+    const uint64_t i = w * kBlock + threadIdx.x;
+    if (i < lv.m[0]) {
+      const uint64_t off = i * leaf_size;
+      const uint64_t len = total - off < leaf_size ? total - off : leaf_size;
+      Lane A[25];
+      kb::sponge_hash<V>(A, data + off, len, V, row);
+      kb::store_digest<V>(nodes + lv.off[0] + i * D, A, V);
+    }
+  }
+  for (int k = 0; k < levels; ++k) {
+    const int l = first + k;  // reading level l, writing level l + 1
+    __syncthreads();
+    const uint64_t span = static_cast<uint64_t>(kBlock) >> (k + 1);
+    const uint64_t j = w * span + threadIdx.x;
+    if (threadIdx.x < span && j < lv.m[l + 1]) {
+      const uint8_t* src = nodes + lv.off[l] + 2 * j * D;
+      uint8_t* dst = nodes + lv.off[l + 1] + j * D;
+      if (2 * j + 1 < lv.m[l]) {
+        Lane A[25];
+        kb::sponge_hash<V>(A, src, 2 * D, V, row);
+        kb::store_digest<V>(dst, A, V);
+      } else {
+        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+        for (int q = 0; q < static_cast<int>(D / 4); ++q) d32[q] = s32[q];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -176,159 +234,197 @@ __global__ void k_reset(uint32_t* __restrict__ meta, uint32_t words) {
     meta[k] = 0u;
 }
 
-// Active lanes holding the same key as this lane (a software match-any):
-// one pass per distinct key in the wave.
-__device__ __forceinline__ uint64_t same_key_lanes(uint32_t key) {
-  uint64_t remaining = __ballot(1);
-  uint64_t mine = 0;
-  while (remaining) {
-    const int leader = __ffsll(static_cast<unsigned long long>(remaining)) - 1;
-    const uint32_t k0 = __shfl(key, leader);
-    const uint64_t m = __ballot(key == k0) & remaining;
-    if (key == k0) mine = m;
-    remaining &= ~m;
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t o = __shfl_xor(v, d);
+    v = o > v ? o : v;
   }
-  return mine;
+  return v;
 }
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t below = lane ? (~0ull >> (64u - lane)) : 0ull;
-  return static_cast<uint32_t>(__popcll(mask & below));
+template <int V>
+__device__ __forceinline__ uint32_t key_at(const uint64_t* __restrict__ lens,
+                                           const uint8_t* __restrict__ vars, uint64_t i) {
+  return key_of(blocks_of<V>(lens[i], V == kMixed ? vars[i] : V));
 }
 
+// Histogram of block-count keys and the lane slots arrival order would
+// idle.  Wave c of the grid-stride loop takes messages [64 c, 64 c + 64):
+// when all 64 share one key (the common case for uniform batches) one LDS
+// atomic records them; otherwise every lane adds its own key and the wave's
+// idle slots (64 * max - sum) are accumulated.
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ lens,
                                                   const uint8_t* __restrict__ vars, uint64_t n,
                                                   uint32_t* __restrict__ hist,
                                                   uint32_t* __restrict__ ctl) {
   __shared__ uint32_t lhist[kKeyBins];
-  __shared__ unsigned long long lsum_nb, lsum_wave;
+  __shared__ unsigned long long luseful, lidle;
   __shared__ uint32_t lmax;
   for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock) lhist[k] = 0u;
   if (threadIdx.x == 0) {
-    lsum_nb = 0ull;
-    lsum_wave = 0ull;
+    luseful = 0ull;
+    lidle = 0ull;
     lmax = 0u;
   }
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t waves = static_cast<uint64_t>(gridDim.x) * (kBlock / 64);
   const uint64_t wave_id = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
-  uint64_t acc_nb = 0, acc_wave = 0;
-  uint32_t acc_max = 0;
+  uint64_t useful = 0, idle = 0;
+  uint32_t kmax = 0;
   for (uint64_t c = wave_id; c * 64u < n; c += waves) {
     const uint64_t i = c * 64u + lane;
-    uint64_t nb = 0;
-    if (i < n) nb = blocks_of<V>(lens[i], V == kMixed ? vars[i] : V);
-    // 64 * max nb over the wave, and the sum of nb
-    uint64_t mx = nb, sm = nb;
-    for (int d = 32; d >= 1; d >>= 1) {
-      const uint64_t omx = __shfl_xor(mx, d);
-      const uint64_t osm = __shfl_xor(sm, d);
-      mx = omx > mx ? omx : mx;
-      sm += osm;
-    }
-    acc_nb += sm;
-    acc_wave += 64u * mx;
-    if (i < n) {
-      const uint32_t key = key_of(nb);
-      acc_max = key > acc_max ? key : acc_max;
-      const uint64_t peers = same_key_lanes(key);
-      if (lanes_below(peers) == 0) atomicAdd(&lhist[key], static_cast<uint32_t>(__popcll(peers)));
+    const bool valid = i < n;
+    const uint32_t key = valid ? key_at<V>(lens, vars, i) : 0u;
+    const uint32_t key0 = __builtin_amdgcn_readfirstlane(key);  // lane 0 is always valid
+    kmax = key > kmax ? key : kmax;
+    const uint64_t cnt = n - c * 64u < 64u ? n - c * 64u : 64u;
+    if (__ballot(valid && key != key0) == 0) {
+      if (lane == 0) atomicAdd(&lhist[key0], static_cast<uint32_t>(cnt));
+      useful += static_cast<uint64_t>(key0) * cnt;
+    } else {
+      if (valid) atomicAdd(&lhist[key], 1u);
+      const uint32_t sm = wave_sum(key), mx = wave_max(key);
+      useful += sm;
+      idle += static_cast<uint64_t>(mx) * cnt - sm;
     }
   }
   if (lane == 0) {
-    atomicAdd(&lsum_nb, static_cast<unsigned long long>(acc_nb));
-    atomicAdd(&lsum_wave, static_cast<unsigned long long>(acc_wave));
+    atomicAdd(&luseful, static_cast<unsigned long long>(useful));
+    atomicAdd(&lidle, static_cast<unsigned long long>(idle));
   }
-  atomicMax(&lmax, acc_max);
+  atomicMax(&lmax, kmax);
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock)
     if (lhist[k]) atomicAdd(&hist[k], lhist[k]);
   if (threadIdx.x == 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_SUM_NB]), lsum_nb);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_SUM_WAVE]), lsum_wave);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_USEFUL]), luseful);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_IDLE]), lidle);
     atomicMax(&ctl[CTL_MAXKEY], lmax);
   }
 }
 
-// Block-wide exclusive scan of one value per thread (kPlanThreads threads).
-__device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* scratch, uint64_t* total) {
+// Block-wide inclusive scan of one value per thread (kPlanThreads threads).
+__device__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* scratch) {
   const uint32_t t = threadIdx.x;
   scratch[t] = v;
   __syncthreads();
   for (uint32_t d = 1; d < kPlanThreads; d <<= 1) {
-    const uint64_t add = t >= d ? scratch[t - d] : 0ull;
+    const uint32_t add = t >= d ? scratch[t - d] : 0u;
     __syncthreads();
     scratch[t] += add;
     __syncthreads();
   }
-  const uint64_t incl = scratch[t];
-  *total = scratch[kPlanThreads - 1];
+  const uint32_t r = scratch[t];
   __syncthreads();
-  return incl - v;
+  return r;
 }
 
-// One workgroup of kPlanThreads threads.  Thread t owns the four bins of
-// descending-key rank 4t .. 4t+3 (rank r is key kKeyBins - 1 - r).
-__global__ __launch_bounds__(kPlanThreads) void k_plan(uint32_t* __restrict__ hist,
+// Messages per queue item in a bucket of `key` blocks: 64 lanes times enough
+// messages per lane to give about `steps` permutations per lane.
+__device__ __forceinline__ uint32_t item_msgs(uint32_t key, uint32_t steps) {
+  const uint32_t g = key >= steps ? 1u : steps / (key ? key : 1u);
+  return 64u * g;
+}
+
+// One workgroup of kPlanThreads threads.  Bucket rank r = kKeyBins - 1 - key
+// orders buckets longest first; thread t owns ranks 4t .. 4t+3.  Writes the
+// bucket starts (start[key]) and the inclusive prefix of queue items per rank
+// (iend[r]).
+__global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restrict__ hist,
                                                        uint32_t* __restrict__ start,
-                                                       uint32_t* __restrict__ ctl,
-                                                       WorkItem* __restrict__ items, uint64_t n,
-                                                       uint32_t steps_per_item,
-                                                       int allow_identity, int force_sort) {
-  __shared__ uint64_t scratch[kPlanThreads];
+                                                       uint32_t* __restrict__ iend,
+                                                       uint32_t* __restrict__ ctl, uint64_t n,
+                                                       uint32_t steps, uint32_t n_simds,
+                                                       int force_sort) {
+  __shared__ uint32_t scratch[kPlanThreads];
   __shared__ uint32_t identity;
   const uint32_t t = threadIdx.x;
   if (t == 0) {
-    const uint64_t sum_nb = *reinterpret_cast<unsigned long long*>(&ctl[CTL_SUM_NB]);
-    const uint64_t sum_wave = *reinterpret_cast<unsigned long long*>(&ctl[CTL_SUM_WAVE]);
-    // arrival order is kept when its waves waste at most 2 % of lane slots
-    identity = (!force_sort && allow_identity && sum_wave * 50u <= sum_nb * 51u) ? 1u : 0u;
+    const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
+    const uint64_t idle = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_IDLE]);
+    identity = (!force_sort && idle * 50u <= useful) ? 1u : 0u;
     ctl[CTL_IDENTITY] = identity;
+    if (identity) {
+      const uint64_t avg = useful / (n ? n : 1);
+      const uint32_t per = item_msgs(avg > 0xFFFFu ? 0xFFFFu : static_cast<uint32_t>(avg), steps);
+      ctl[CTL_ID_PER] = per;
+      ctl[CTL_NITEMS] = static_cast<uint32_t>((n + per - 1) / per);
+      ctl[CTL_PRIO_ITEMS] = 0u;
+      ctl[CTL_PRIO_KEY] = 0xFFFFFFFFu;
+    }
   }
   __syncthreads();
-  if (identity) {
-    const uint64_t sum_nb = *reinterpret_cast<unsigned long long*>(&ctl[CTL_SUM_NB]);
-    const uint64_t avg = sum_nb / (n ? n : 1);
-    const uint64_t g = avg >= steps_per_item ? 1u : steps_per_item / (avg ? avg : 1);
-    const uint64_t per = 64u * g;
-    const uint64_t m = (n + per - 1) / per;
-    for (uint64_t k = t; k < m; k += kPlanThreads) {
-      const uint64_t b = k * per, e = b + per < n ? b + per : n;
-      items[k] = WorkItem{static_cast<uint32_t>(b), static_cast<uint32_t>(e)};
-    }
-    if (t == 0) ctl[CTL_NITEMS] = static_cast<uint32_t>(m);
-    return;
-  }
-  uint32_t cnt[4], per[4];
-  uint64_t c_sum = 0, it_sum = 0;
+  if (identity) return;
+  uint32_t cnt[4], items[4], c_sum = 0, it_sum = 0;
   for (int q = 0; q < 4; ++q) {
     const uint32_t key = kKeyBins - 1u - (4u * t + q);
     cnt[q] = key ? hist[key] : 0u;
-    const uint32_t g = key >= steps_per_item ? 1u : steps_per_item / (key ? key : 1u);
-    per[q] = 64u * g;
+    const uint32_t per = item_msgs(key, steps);
+    items[q] = (cnt[q] + per - 1u) / per;
     c_sum += cnt[q];
-    it_sum += (cnt[q] + per[q] - 1u) / per[q];
+    it_sum += items[q];
   }
-  uint64_t total;
-  uint64_t c_base = block_exclusive_scan(c_sum, scratch, &total);
-  uint64_t it_base = block_exclusive_scan(it_sum, scratch, &total);
-  if (t == 0) ctl[CTL_NITEMS] = static_cast<uint32_t>(total);
+  uint32_t c_base = block_inclusive_scan(c_sum, scratch) - c_sum;
+  uint32_t it_run = block_inclusive_scan(it_sum, scratch) - it_sum;
   for (int q = 0; q < 4; ++q) {
     const uint32_t key = kKeyBins - 1u - (4u * t + q);
-    start[key] = static_cast<uint32_t>(c_base);
-    for (uint32_t b = 0; b < cnt[q]; b += per[q]) {
-      const uint32_t e = b + per[q] < cnt[q] ? b + per[q] : cnt[q];
-      items[it_base++] = WorkItem{static_cast<uint32_t>(c_base + b), static_cast<uint32_t>(c_base + e)};
-    }
+    start[key] = c_base;
     c_base += cnt[q];
+    it_run += items[q];
+    iend[4u * t + q] = it_run;
+  }
+  if (t == kPlanThreads - 1) {
+    ctl[CTL_NITEMS] = it_run;
+    // The first n_simds / 2 items run at high priority if they are at least
+    // twice as long as the average message.
+    const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
+    const uint64_t avg = useful / (n ? n : 1);
+    ctl[CTL_PRIO_ITEMS] = n_simds / 2u;
+    ctl[CTL_PRIO_KEY] = static_cast<uint32_t>(2u * avg + 2u);
   }
 }
 
-// Counting-sort scatter: workgroup w handles messages [w * tile, (w+1) * tile)
-// and reserves one range per non-empty bin with a single global atomic.
+// Queue item t: its bucket (the smallest rank r with iend[r] > t) and its
+// range of positions in the bucketed order.
+__global__ __launch_bounds__(kBlock) void k_items(const uint32_t* __restrict__ hist,
+                                                  const uint32_t* __restrict__ start,
+                                                  const uint32_t* __restrict__ iend,
+                                                  const uint32_t* __restrict__ ctl, uint64_t n,
+                                                  uint32_t steps, WorkItem* __restrict__ items) {
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= ctl[CTL_NITEMS]) return;
+  if (ctl[CTL_IDENTITY]) {
+    const uint64_t per = ctl[CTL_ID_PER];
+    const uint64_t b = t * per, e = b + per < n ? b + per : n;
+    items[t] = WorkItem{static_cast<uint32_t>(b), static_cast<uint32_t>(e), 0u, 0u};
+    return;
+  }
+  uint32_t lo = 0, hi = kKeyBins - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (iend[mid] > t)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const uint32_t key = kKeyBins - 1u - lo;
+  const uint32_t per = item_msgs(key, steps);
+  const uint32_t first_item = lo ? iend[lo - 1] : 0u;
+  const uint32_t b = start[key] + (t - first_item) * per;
+  const uint32_t bucket_end = start[key] + hist[key];
+  items[t] = WorkItem{b, b + per < bucket_end ? b + per : bucket_end, key, 0u};
+}
+
+// Counting-sort scatter: workgroup w handles messages [w * tile, (w+1) * tile),
+// reserves one range per non-empty bucket with a single global atomic, and
+// ranks its messages inside each range with LDS atomics.
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__ lens,
                                                     const uint8_t* __restrict__ vars, uint64_t n,
@@ -343,13 +439,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__
   __syncthreads();
   const uint64_t first = static_cast<uint64_t>(blockIdx.x) * kScatterTile;
   const uint64_t last = first + kScatterTile < n ? first + kScatterTile : n;
-  for (uint64_t i0 = first; i0 < last; i0 += kBlock) {
-    const uint64_t i = i0 + threadIdx.x;
-    if (i < last) {
-      const uint32_t key = key_of(blocks_of<V>(lens[i], V == kMixed ? vars[i] : V));
-      const uint64_t peers = same_key_lanes(key);
-      if (lanes_below(peers) == 0) atomicAdd(&lcount[key], static_cast<uint32_t>(__popcll(peers)));
-    }
+  uint32_t keys[kScatterTile / kBlock];
+#pragma unroll
+  for (int q = 0; q < kScatterTile / kBlock; ++q) {
+    const uint64_t i = first + static_cast<uint64_t>(q) * kBlock + threadIdx.x;
+    keys[q] = i < last ? key_at<V>(lens, vars, i) : 0u;
+    if (i < last) atomicAdd(&lcount[keys[q]], 1u);
   }
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock) {
@@ -358,17 +453,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__
     lcount[k] = 0u;
   }
   __syncthreads();
-  for (uint64_t i0 = first; i0 < last; i0 += kBlock) {
-    const uint64_t i = i0 + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kScatterTile / kBlock; ++q) {
+    const uint64_t i = first + static_cast<uint64_t>(q) * kBlock + threadIdx.x;
     if (i < last) {
-      const uint32_t key = key_of(blocks_of<V>(lens[i], V == kMixed ? vars[i] : V));
-      const uint64_t peers = same_key_lanes(key);
-      const uint32_t rank = lanes_below(peers);
-      uint32_t base = 0;
-      if (rank == 0) base = atomicAdd(&lcount[key], static_cast<uint32_t>(__popcll(peers)));
-      const int leader = __ffsll(static_cast<unsigned long long>(peers)) - 1;
-      base = __shfl(base, leader);
-      order[lbase[key] + base + rank] = static_cast<uint32_t>(i);
+      const uint32_t rank = atomicAdd(&lcount[keys[q]], 1u);
+      order[lbase[keys[q]] + rank] = static_cast<uint32_t>(i);
     }
   }
 }
@@ -396,7 +486,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 struct Workspace {
-  uint32_t* meta = nullptr;  // hist | start | cursor | ctl
+  uint32_t* meta = nullptr;  // hist | start | cursor | iend | ctl
   uint32_t* order = nullptr;
   uint64_t order_cap = 0;
   WorkItem* items = nullptr;
@@ -406,7 +496,7 @@ struct Workspace {
   uint32_t* host_hist = nullptr;  // pinned, for the per-bucket form
 };
 
-constexpr uint32_t kMetaWords = 3 * kKeyBins + CTL_WORDS;
+constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS;
 
 // Measurement hook state (keccak_timing_*): event pairs around kernel launches.
 struct Timing {
@@ -478,6 +568,10 @@ int grow(void** ptr, uint64_t* cap, uint64_t need, hipStream_t stream) {
   return KB_OK;
 }
 
+// Queue items of a batch of n messages: ceil(n / 64) in arrival order, or at
+// most one partial item per bucket more than that when bucketed.
+uint64_t max_items(uint64_t n) { return n / 64 + kKeyBins + 1; }
+
 int get_ws(hipStream_t stream, uint64_t msgs, uint64_t tree_bytes, Workspace** out) {
   int dev = 0;
   KB_HIP(hipGetDevice(&dev));
@@ -491,7 +585,7 @@ int get_ws(hipStream_t stream, uint64_t msgs, uint64_t tree_bytes, Workspace** o
   if (msgs) {
     int rc = grow(reinterpret_cast<void**>(&w.order), &w.order_cap, msgs * 4ull, stream);
     if (rc) return rc;
-    const uint64_t items = msgs / 64 + kKeyBins + 1;
+    const uint64_t items = max_items(msgs);
     rc = grow(reinterpret_cast<void**>(&w.items), &w.items_cap, items * sizeof(WorkItem), stream);
     if (rc) return rc;
   }
@@ -533,17 +627,26 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, h
   uint32_t* hist = w.meta;
   uint32_t* start = w.meta + kKeyBins;
   uint32_t* cursor = w.meta + 2 * kKeyBins;
-  uint32_t* ctl = w.meta + 3 * kKeyBins;
+  uint32_t* iend = w.meta + 3 * kKeyBins;
+  uint32_t* ctl = w.meta + 4 * kKeyBins;
+  int dev = 0, cus = 0;
+  KB_HIP(hipGetDevice(&dev));
+  int rc = cu_count(dev, &cus);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_reset, dim3(16), dim3(256), 0, s, w.meta, kMetaWords);
   KB_HIP(hipGetLastError());
-  uint64_t cblocks = (b.n + 64 * 16 - 1) / (64 * 16);  // >= 16 waves of work per block
-  if (cblocks > 2048) cblocks = 2048;
-  if (cblocks < 1) cblocks = 1;
+  // about 32 waves of 64 messages per workgroup, at most 4 workgroups per CU
+  uint64_t cblocks = (b.n + 64 * 32 - 1) / (64 * 32);
+  if (cblocks > static_cast<uint64_t>(4 * cus)) cblocks = 4 * cus;
   hipLaunchKernelGGL(k_count<V>, dim3(static_cast<uint32_t>(cblocks)), dim3(kBlock), 0, s, b.lens,
                      b.vars, b.n, hist, ctl);
   KB_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, hist, start, ctl, w.items, b.n,
-                     steps, force_sort ? 0 : 1, force_sort);
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, hist, start, iend, ctl, b.n, steps,
+                     static_cast<uint32_t>(4 * cus), force_sort);
+  KB_HIP(hipGetLastError());
+  const uint64_t iblocks = (max_items(b.n) + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_items, dim3(static_cast<uint32_t>(iblocks)), dim3(kBlock), 0, s, hist, start,
+                     iend, ctl, b.n, steps, w.items);
   KB_HIP(hipGetLastError());
   const uint64_t sblocks = (b.n + kScatterTile - 1) / kScatterTile;
   hipLaunchKernelGGL(k_scatter<V>, dim3(static_cast<uint32_t>(sblocks)), dim3(kBlock), 0, s,
@@ -593,7 +696,7 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s) {
   {
     TimedLaunch tl(s);
     hipLaunchKernelGGL(k_persistent<V>, dim3(grid), dim3(kBlock), 0, s, b.data, b.offs, b.lens,
-                       b.vars, w->order, w->items, w->meta + 3 * kKeyBins, b.out);
+                       b.vars, w->order, w->items, w->meta + 4 * kKeyBins, b.out);
   }
   KB_HIP(hipGetLastError());
   return KB_OK;
@@ -636,35 +739,31 @@ int batch_entry(int variant, const uint8_t* vars, const uint8_t* data, const uin
 template <int V>
 int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* root, hipStream_t s) {
   constexpr uint64_t D = kb::digest_bytes_of(V);
-  const uint64_t n = total ? (total + leaf - 1) / leaf : 1;
-  const uint64_t half = (n + 1) / 2;
-  Workspace* w = nullptr;
-  int rc = get_ws(s, 0, (n + half) * D, &w);
-  if (rc) return rc;
-  uint8_t* a = w->tree;
-  uint8_t* c = w->tree + n * D;
-  uint64_t blocks = (n + kBlock - 1) / kBlock;
-  {
-    TimedLaunch tl(s);
-    hipLaunchKernelGGL(k_strided<V>, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data,
-                       leaf, leaf, total, n, a);
+  TreeLevels lv{};
+  lv.m[0] = total ? (total + leaf - 1) / leaf : 1;
+  lv.off[0] = 0;
+  int L = 0;  // levels above the leaves
+  while (lv.m[L] > 1) {
+    lv.m[L + 1] = (lv.m[L] + 1) / 2;
+    lv.off[L + 1] = lv.off[L] + lv.m[L] * D;
+    ++L;
   }
-  KB_HIP(hipGetLastError());
-  for (uint64_t m = n; m > 1; m = (m + 1) / 2) {
-    const uint64_t pairs = m / 2;
-    blocks = (pairs + kBlock - 1) / kBlock;
+  Workspace* w = nullptr;
+  int rc = get_ws(s, 0, lv.off[L] + D, &w);
+  if (rc) return rc;
+  int first = 0;
+  do {
+    const int levels = L - first < 8 ? L - first : 8;
+    const uint64_t blocks = (lv.m[first] + kBlock - 1) / kBlock;
     {
       TimedLaunch tl(s);
-      hipLaunchKernelGGL(k_strided<V>, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, a,
-                         2 * D, 2 * D, pairs * 2 * D, pairs, c);
+      hipLaunchKernelGGL(k_tree<V>, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data,
+                         total, leaf, w->tree, first, levels, lv);
     }
     KB_HIP(hipGetLastError());
-    if (m & 1) KB_HIP(hipMemcpyAsync(c + pairs * D, a + (m - 1) * D, D, hipMemcpyDeviceToDevice, s));
-    uint8_t* t = a;
-    a = c;
-    c = t;
-  }
-  KB_HIP(hipMemcpyAsync(root, a, D, hipMemcpyDeviceToDevice, s));
+    first += levels;
+  } while (first < L);
+  KB_HIP(hipMemcpyAsync(root, w->tree + lv.off[L], D, hipMemcpyDeviceToDevice, s));
   return KB_OK;
 }
 
@@ -725,7 +824,7 @@ int keccak_rate_bytes(int variant) {
 int keccak_reserve(uint64_t max_msgs, uint64_t max_leaves, hipStream_t stream) {
   g_err.clear();
   Workspace* w = nullptr;
-  const uint64_t tree = max_leaves ? (max_leaves + (max_leaves + 1) / 2) * 64ull : 0ull;
+  const uint64_t tree = max_leaves ? (2 * max_leaves + 1) * 64ull : 0ull;
   return get_ws(stream, max_msgs, tree, &w);
 }
 
