@@ -54,17 +54,20 @@ constexpr int kScatterTile = 4096;  // messages per scatter workgroup
 
 // control words (uint32 indices into the ctl area)
 enum : int {
-  CTL_QUEUE = 0,       // persistent queue counter
-  CTL_NITEMS = 1,      // number of queue items
-  CTL_IDENTITY = 2,    // 1: arrival order kept, order[] unused
-  CTL_MAXKEY = 3,      // largest block-count key seen
-  CTL_USEFUL = 4,      // uint64: sum of (clamped) block counts (words 4, 5)
-  CTL_IDLE = 6,        // uint64: lane-slots arrival-order waves would idle (words 6, 7)
-  CTL_ID_PER = 8,      // arrival order: messages per queue item
-  CTL_PRIO_ITEMS = 9,  // items [0, PRIO_ITEMS) with key >= PRIO_KEY run at high priority
-  CTL_PRIO_KEY = 10,
+  CTL_QUEUE = 0,     // uint64 (words 0, 1): items taken from the front | from the back << 32
+  CTL_NITEMS = 2,    // number of queue items
+  CTL_IDENTITY = 3,  // 1: arrival order kept, order[] unused
+  CTL_MAXKEY = 4,    // largest block-count key seen
+  CTL_ID_PER = 5,    // arrival order: messages per queue item
+  CTL_USEFUL = 6,    // uint64 (words 6, 7): sum of (clamped) block counts
+  CTL_IDLE = 8,      // uint64 (words 8, 9): lane-slots arrival-order waves would idle
   CTL_WORDS = 64
 };
+
+// One flag per SIMD of the chip, indexed from the wave's hardware id
+// (XCC, shader engine, shader array, CU, SIMD); the first wave to claim its
+// SIMD's flag takes queue items from the front.
+constexpr uint32_t kSimdSlots = 8 * 8 * 2 * 16 * 4;
 
 struct WorkItem {
   uint32_t begin, end;  // positions in order[] (message indices in arrival order)
@@ -98,7 +101,8 @@ __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
                                              const uint64_t* __restrict__ offs,
                                              const uint64_t* __restrict__ lens,
                                              const uint8_t* __restrict__ vars, uint64_t i,
-                                             uint8_t* __restrict__ out, uint32_t* row) {
+                                             uint8_t* __restrict__ out, uint32_t* wave_lds,
+                                             uint32_t lane) {
   int var = V;
   if constexpr (V == kMixed) var = vars[i];
   uint8_t* o = out + i * static_cast<uint64_t>(out_stride<V>());
@@ -109,7 +113,7 @@ __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
     return;
   }
   Lane A[25];
-  kb::sponge_hash<V>(A, data + offs[i], lens[i], var, row);
+  kb::sponge_hash<V>(A, data + offs[i], lens[i], var, wave_lds, lane);
   kb::store_digest<V>(o, A, var);
 }
 
@@ -128,44 +132,68 @@ __global__ __launch_bounds__(kBlock) void k_plain(const uint8_t* __restrict__ da
                                                   uint64_t first, uint64_t count,
                                                   uint8_t* __restrict__ out) {
   using S = SpongeShape<V>;
-  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
+  __shared__ __align__(16) uint32_t lds[(kBlock / 64) * S::kWaveDw];
+  uint32_t* wave_lds = lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::kWaveDw;
   const uint64_t p = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (p >= count) return;
   const uint64_t i = order ? order[first + p] : first + p;
-  hash_message<V>(data, offs, lens, vars, i, out, lds + threadIdx.x * S::kRowDw);
+  hash_message<V>(data, offs, lens, vars, i, out, wave_lds, threadIdx.x & 63u);
 }
 
 // Persistent form: waves pop queue items until the queue is drained.  Every
 // wave leaves the loop once the counter passes the item count, so the grid
 // always drains.
+// Index of the SIMD this wave runs on, from the HW_ID register (SIMD [5:4],
+// CU [11:8], SH [12], SE [15:13]) and XCC_ID [3:0].  Used only to spread the
+// front-of-queue waves one per SIMD; a wrong index costs balance, never
+// correctness.
+__device__ __forceinline__ uint32_t simd_slot() {
+  const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);
+  const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u;
+  const uint32_t simd = (hw >> 4) & 3u, cu = (hw >> 8) & 15u, sh = (hw >> 12) & 1u,
+                 se = (hw >> 13) & 7u;
+  return ((((xcc * 8u + se) * 2u + sh) * 16u + cu) * 4u) + simd;
+}
+
+// Persistent form.  Queue items are ordered longest first.  On each SIMD one
+// wave (the first to claim the SIMD's flag) takes items from the front at
+// raised issue priority, so the long absorb chains that bound the makespan
+// run back to back at full rate; the other resident waves take the shortest
+// items from the back and fill the issue slots the front wave leaves idle.
+// Both ends advance one packed 64-bit counter, so no item is taken twice, and
+// every wave leaves once the two ends meet, so the grid always drains.  In
+// arrival order (uniform work) every wave takes from the front at normal
+// priority.
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_persistent(
     const uint8_t* __restrict__ data, const uint64_t* __restrict__ offs,
     const uint64_t* __restrict__ lens, const uint8_t* __restrict__ vars,
     const uint32_t* __restrict__ order, const WorkItem* __restrict__ items,
-    uint32_t* __restrict__ ctl, uint8_t* __restrict__ out) {
+    uint32_t* __restrict__ ctl, uint32_t* __restrict__ simd_flags, uint8_t* __restrict__ out) {
   using S = SpongeShape<V>;
-  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
-  uint32_t* row = lds + threadIdx.x * S::kRowDw;
+  __shared__ __align__(16) uint32_t lds[(kBlock / 64) * S::kWaveDw];
+  uint32_t* wave_lds = lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::kWaveDw;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t n_items = ctl[CTL_NITEMS];
-  const uint32_t prio_items = ctl[CTL_PRIO_ITEMS];
-  const uint32_t prio_key = ctl[CTL_PRIO_KEY];
-  const uint32_t* ord = ctl[CTL_IDENTITY] ? nullptr : order;
+  const bool sorted = ctl[CTL_IDENTITY] == 0u;
+  const uint32_t* ord = sorted ? order : nullptr;
+  uint32_t claim = 0;
+  if (sorted && lane == 0) claim = atomicCAS(&simd_flags[simd_slot()], 0u, 1u) == 0u ? 1u : 0u;
+  const bool front = !sorted || __builtin_amdgcn_readfirstlane(__shfl(claim, 0)) != 0u;
+  if (sorted && front) __builtin_amdgcn_s_setprio(3);
+  unsigned long long* queue = reinterpret_cast<unsigned long long*>(&ctl[CTL_QUEUE]);
+  const unsigned long long step = front ? 1ull : (1ull << 32);
   for (;;) {
-    uint32_t t = 0;
-    if (lane == 0)
-      t = __hip_atomic_fetch_add(&ctl[CTL_QUEUE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-    if (t >= n_items) break;
+    unsigned long long old = 0;
+    if (lane == 0) old = __hip_atomic_fetch_add(queue, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t head = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old), 0));
+    const uint32_t tail = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old >> 32), 0));
+    if (static_cast<uint64_t>(head) + tail >= n_items) break;
+    const uint32_t t = front ? head : n_items - 1u - tail;
     const WorkItem it = items[t];
-    if (t < prio_items && it.key >= prio_key)
-      __builtin_amdgcn_s_setprio(3);
-    else
-      __builtin_amdgcn_s_setprio(0);
     for (uint32_t pos = it.begin + lane; pos < it.end; pos += 64u) {
       const uint64_t i = ord ? ord[pos] : pos;
-      hash_message<V>(data, offs, lens, vars, i, out, row);
+      hash_message<V>(data, offs, lens, vars, i, out, wave_lds, lane);
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -190,8 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ dat
                                                  int first, int levels, TreeLevels lv) {
   using S = SpongeShape<V>;
   constexpr uint64_t D = kb::digest_bytes_of(V);
-  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
-  uint32_t* row = lds + threadIdx.x * S::kRowDw;
+  __shared__ __align__(16) uint32_t lds[(kBlock / 64) * S::kWaveDw];
+  uint32_t* wave_lds = lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::kWaveDw;
+  const uint32_t lane = threadIdx.x & 63u;
   const uint64_t w = blockIdx.x;
   if (first == 0) {
     const uint64_t i = w * kBlock + threadIdx.x;
@@ -199,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ dat
       const uint64_t off = i * leaf_size;
       const uint64_t len = total - off < leaf_size ? total - off : leaf_size;
       Lane A[25];
-      kb::sponge_hash<V>(A, data + off, len, V, row);
+      kb::sponge_hash<V>(A, data + off, len, V, wave_lds, lane);
       kb::store_digest<V>(nodes + lv.off[0] + i * D, A, V);
     }
   }
@@ -213,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ dat
       uint8_t* dst = nodes + lv.off[l + 1] + j * D;
       if (2 * j + 1 < lv.m[l]) {
         Lane A[25];
-        kb::sponge_hash<V>(A, src, 2 * D, V, row);
+        kb::sponge_hash<V>(A, src, 2 * D, V, wave_lds, lane);
         kb::store_digest<V>(dst, A, V);
       } else {
         const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
@@ -254,10 +283,13 @@ __device__ __forceinline__ uint32_t key_at(const uint64_t* __restrict__ lens,
 }
 
 // Histogram of block-count keys and the lane slots arrival order would
-// idle.  Wave c of the grid-stride loop takes messages [64 c, 64 c + 64):
-// when all 64 share one key (the common case for uniform batches) one LDS
-// atomic records them; otherwise every lane adds its own key and the wave's
-// idle slots (64 * max - sum) are accumulated.
+// idle.  A wave takes kCountUnroll consecutive 64-message chunks per pass,
+// issuing all their length loads before using any.  When all 64 messages of
+// a chunk share one key (the common case for uniform batches) one LDS atomic
+// records them; otherwise every lane adds its own key and the chunk's idle
+// slots (count * max - sum) are accumulated.
+constexpr int kCountUnroll = 8;
+
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ lens,
                                                   const uint8_t* __restrict__ vars, uint64_t n,
@@ -278,21 +310,35 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ l
   const uint64_t wave_id = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
   uint64_t useful = 0, idle = 0;
   uint32_t kmax = 0;
-  for (uint64_t c = wave_id; c * 64u < n; c += waves) {
-    const uint64_t i = c * 64u + lane;
-    const bool valid = i < n;
-    const uint32_t key = valid ? key_at<V>(lens, vars, i) : 0u;
-    const uint32_t key0 = __builtin_amdgcn_readfirstlane(key);  // lane 0 is always valid
-    kmax = key > kmax ? key : kmax;
-    const uint64_t cnt = n - c * 64u < 64u ? n - c * 64u : 64u;
-    if (__ballot(valid && key != key0) == 0) {
-      if (lane == 0) atomicAdd(&lhist[key0], static_cast<uint32_t>(cnt));
-      useful += static_cast<uint64_t>(key0) * cnt;
-    } else {
-      if (valid) atomicAdd(&lhist[key], 1u);
-      const uint32_t sm = wave_sum(key), mx = wave_max(key);
-      useful += sm;
-      idle += static_cast<uint64_t>(mx) * cnt - sm;
+  for (uint64_t c0 = wave_id * kCountUnroll; c0 * 64u < n; c0 += waves * kCountUnroll) {
+    uint64_t len[kCountUnroll];
+    int var[kCountUnroll];
+#pragma unroll
+    for (int u = 0; u < kCountUnroll; ++u) {
+      const uint64_t i = (c0 + u) * 64u + lane;
+      len[u] = i < n ? lens[i] : 0u;
+      var[u] = V;
+      if constexpr (V == kMixed) var[u] = i < n ? vars[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kCountUnroll; ++u) {
+      const uint64_t c = c0 + u;
+      if (c * 64u >= n) break;
+      const uint64_t i = c * 64u + lane;
+      const bool valid = i < n;
+      const uint32_t key = valid ? key_of(blocks_of<V>(len[u], var[u])) : 0u;
+      const uint32_t key0 = __builtin_amdgcn_readfirstlane(key);  // lane 0 is always valid
+      kmax = key > kmax ? key : kmax;
+      const uint64_t cnt = n - c * 64u < 64u ? n - c * 64u : 64u;
+      if (__ballot(valid && key != key0) == 0) {
+        if (lane == 0) atomicAdd(&lhist[key0], static_cast<uint32_t>(cnt));
+        useful += static_cast<uint64_t>(key0) * cnt;
+      } else {
+        if (valid) atomicAdd(&lhist[key], 1u);
+        const uint32_t sm = wave_sum(key), mx = wave_max(key);
+        useful += sm;
+        idle += static_cast<uint64_t>(mx) * cnt - sm;
+      }
     }
   }
   if (lane == 0) {
@@ -341,8 +387,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
                                                        uint32_t* __restrict__ start,
                                                        uint32_t* __restrict__ iend,
                                                        uint32_t* __restrict__ ctl, uint64_t n,
-                                                       uint32_t steps, uint32_t n_simds,
-                                                       int force_sort) {
+                                                       uint32_t steps, int force_sort) {
   __shared__ uint32_t scratch[kPlanThreads];
   __shared__ uint32_t identity;
   const uint32_t t = threadIdx.x;
@@ -356,8 +401,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
       const uint32_t per = item_msgs(avg > 0xFFFFu ? 0xFFFFu : static_cast<uint32_t>(avg), steps);
       ctl[CTL_ID_PER] = per;
       ctl[CTL_NITEMS] = static_cast<uint32_t>((n + per - 1) / per);
-      ctl[CTL_PRIO_ITEMS] = 0u;
-      ctl[CTL_PRIO_KEY] = 0xFFFFFFFFu;
     }
   }
   __syncthreads();
@@ -380,15 +423,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
     it_run += items[q];
     iend[4u * t + q] = it_run;
   }
-  if (t == kPlanThreads - 1) {
-    ctl[CTL_NITEMS] = it_run;
-    // The first n_simds / 2 items run at high priority if they are at least
-    // twice as long as the average message.
-    const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
-    const uint64_t avg = useful / (n ? n : 1);
-    ctl[CTL_PRIO_ITEMS] = n_simds / 2u;
-    ctl[CTL_PRIO_KEY] = static_cast<uint32_t>(2u * avg + 2u);
-  }
+  if (t == kPlanThreads - 1) ctl[CTL_NITEMS] = it_run;
 }
 
 // Queue item t: its bucket (the smallest rank r with iend[r] > t) and its
@@ -486,7 +521,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 struct Workspace {
-  uint32_t* meta = nullptr;  // hist | start | cursor | iend | ctl
+  uint32_t* meta = nullptr;  // hist | start | cursor | iend | ctl | simd flags
   uint32_t* order = nullptr;
   uint64_t order_cap = 0;
   WorkItem* items = nullptr;
@@ -496,7 +531,7 @@ struct Workspace {
   uint32_t* host_hist = nullptr;  // pinned, for the per-bucket form
 };
 
-constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS;
+constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS + kSimdSlots;
 
 // Measurement hook state (keccak_timing_*): event pairs around kernel launches.
 struct Timing {
@@ -635,14 +670,15 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, h
   if (rc) return rc;
   hipLaunchKernelGGL(k_reset, dim3(16), dim3(256), 0, s, w.meta, kMetaWords);
   KB_HIP(hipGetLastError());
-  // about 32 waves of 64 messages per workgroup, at most 4 workgroups per CU
-  uint64_t cblocks = (b.n + 64 * 32 - 1) / (64 * 32);
+  // about 4 passes of 4 waves x kCountUnroll chunks per workgroup, at most 4
+  // workgroups per CU
+  uint64_t cblocks = (b.n + 64 * 16 * kCountUnroll - 1) / (64 * 16 * kCountUnroll);
   if (cblocks > static_cast<uint64_t>(4 * cus)) cblocks = 4 * cus;
   hipLaunchKernelGGL(k_count<V>, dim3(static_cast<uint32_t>(cblocks)), dim3(kBlock), 0, s, b.lens,
                      b.vars, b.n, hist, ctl);
   KB_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, hist, start, iend, ctl, b.n, steps,
-                     static_cast<uint32_t>(4 * cus), force_sort);
+                     force_sort);
   KB_HIP(hipGetLastError());
   const uint64_t iblocks = (max_items(b.n) + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_items, dim3(static_cast<uint32_t>(iblocks)), dim3(kBlock), 0, s, hist, start,
@@ -696,7 +732,8 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s) {
   {
     TimedLaunch tl(s);
     hipLaunchKernelGGL(k_persistent<V>, dim3(grid), dim3(kBlock), 0, s, b.data, b.offs, b.lens,
-                       b.vars, w->order, w->items, w->meta + 4 * kKeyBins, b.out);
+                       b.vars, w->order, w->items, w->meta + 4 * kKeyBins,
+                       w->meta + 4 * kKeyBins + CTL_WORDS, b.out);
   }
   KB_HIP(hipGetLastError());
   return KB_OK;
