@@ -111,6 +111,91 @@ int keccak_batch_ex(int variant, const uint8_t* d_variants, const uint8_t* d_dat
 int merkle_root(int variant, const uint8_t* d_data, uint64_t total_len, uint64_t leaf_size,
                 uint8_t* d_root, hipStream_t stream);
 
+/*
+ * keccak_autotune -- choose the tile of the persistent form for this batch.
+ * Runs every candidate (steps_per_item in {1, 2, 4, 8, 16, 32} x
+ * waves_per_simd in {1, 2, occupancy maximum}), checks that each candidate's
+ * digests equal the plain form's bit for bit (a candidate that differs is
+ * discarded and counted in *rejected), times the verified ones with HIP
+ * events (median of `reps` runs) and returns the fastest in *best and its
+ * time in *best_ms.  Arguments as keccak_batch_ex; variant -1 = mixed.
+ * Synchronous; allocates two output buffers of the batch's digest size for
+ * its duration.
+ */
+int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_data,
+                    const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n, int reps,
+                    kb_tile* best, double* best_ms, int* rejected, hipStream_t stream);
+
+/*
+ * Graph capture of a whole batch (all scheduling kernels and the hashing
+ * kernel) or a whole tree, for replay with one launch.  The arguments are
+ * bound at capture time: replaying hashes whatever the bound buffers hold
+ * then.  Each graph owns a private workspace (allocated at create, freed at
+ * destroy), so direct calls and other graphs never disturb it; replays of
+ * one graph must not overlap each other (replay it on one stream).  Only
+ * the persistent and plain modes can be captured.
+ */
+typedef struct kb_graph kb_graph;
+int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d_data,
+                        const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n,
+                        uint8_t* d_digests, int mode, const kb_tile* tile, hipStream_t stream,
+                        kb_graph** out);
+int keccak_graph_create_merkle(int variant, const uint8_t* d_data, uint64_t total_len,
+                               uint64_t leaf_size, uint8_t* d_root, hipStream_t stream,
+                               kb_graph** out);
+int keccak_graph_launch(kb_graph* graph, hipStream_t stream);
+int keccak_graph_destroy(kb_graph* graph);
+
+/*
+ * Serving: a continuous-batching request server over a device-resident byte
+ * pool (batch mode of Section 4 applied to a stream of requests).  A request
+ * is a variant and n slices (offset, length) of the pool, given as host
+ * arrays (copied at submit).  A worker thread admits queued requests in
+ * arrival order into steps of at most max_step_msgs messages, keeps up to
+ * steps_in_flight steps on the GPU at once (one HIP stream and one set of
+ * device buffers each, allocated at create), and hashes each step with
+ * keccak_batch_mixed.  A request larger than a step is rejected (KB_ENOMEM).
+ * Results are 64-byte digest slots, one per message, zero past the digest.
+ * Thread-safe: any thread may submit and poll.
+ *
+ * executor (optional): if set, the server never touches the GPU and instead
+ * calls executor(user, variants, offsets, lengths, n, digests) on the worker
+ * thread for every step (host arrays; the callback fills digests[n * 64] and
+ * returns KB_OK).  d_pool is then not dereferenced.
+ */
+typedef int (*kb_step_executor)(void* user, const uint8_t* h_variants, const uint64_t* h_offsets,
+                                const uint64_t* h_lengths, uint64_t n, uint8_t* h_digests);
+typedef struct kb_server_config {
+  const uint8_t* d_pool;   /* device byte pool the requests slice */
+  uint64_t pool_bytes;     /* its size: every slice must lie inside */
+  uint64_t max_step_msgs;  /* message slots per step */
+  int32_t steps_in_flight; /* 1..8 */
+  int32_t reserved;
+  kb_step_executor executor;
+  void* executor_user;
+} kb_server_config;
+typedef struct kb_server_stats {
+  uint64_t steps, messages, bytes, completed, rejected, pending, max_step_msgs_seen;
+  double step_busy_s; /* sum over steps of launch-to-completion time */
+  double span_s;      /* first launch to last completion */
+} kb_server_stats;
+typedef struct kb_server kb_server;
+int keccak_server_create(const kb_server_config* cfg, kb_server** out);
+int keccak_server_submit(kb_server* server, int variant, const uint64_t* h_offsets,
+                         const uint64_t* h_lengths, uint64_t n, uint64_t* request_id);
+/* Ids of finished requests (up to max_ids), waiting up to wait_ms for one. */
+int keccak_server_poll(kb_server* server, uint64_t* ids, uint64_t max_ids, uint64_t* count,
+                       int wait_ms);
+/* Copy a finished request's digests (n * 64 bytes) and latency (submit to
+ * completion, ms) and forget the request. */
+int keccak_server_result(kb_server* server, uint64_t id, uint8_t* h_out, uint64_t out_bytes,
+                         double* latency_ms);
+int keccak_server_stats(kb_server* server, kb_server_stats* out);
+/* Finish every queued request, stop the worker and free the server. */
+int keccak_server_destroy(kb_server* server);
+/* Text of the last server error on the calling host thread. */
+const char* keccak_server_last_error(void);
+
 /* Digest and rate sizes in bytes of a variant; -1 if it is out of range. */
 int keccak_digest_bytes(int variant);
 int keccak_rate_bytes(int variant);
@@ -134,7 +219,7 @@ int keccak_timing_read(double* total_ms, uint64_t* launches);
 
 /* Probe: sustained 32-bit VALU issue rate of the current device (tera
  * lane-operations per second; a grid of 8 waves per SIMD running `iters`
- * iterations of 16 independent 3-input xors per lane) and the shader clock
+ * iterations of 16 independent v_bitop3 chains per lane) and the shader clock
  * seen by that kernel (MHz, from the shader and constant-rate counters).
  * Synchronous; allocates 20 bytes of device memory for its duration. */
 int keccak_probe_valu(uint32_t iters, double* tops, double* sclk_mhz, hipStream_t stream);

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libkbatch.so")
 ARCH = "gfx950"
 
-SOURCES = [os.path.join(CSRC, "kbatch.hip"), os.path.join(CSRC, "probes.hip")]
+SOURCES = [os.path.join(CSRC, "kbatch.hip"), os.path.join(CSRC, "probes.hip"),
+           os.path.join(CSRC, "server.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("keccak_device.h", "sponge_device.h")] + [
     os.path.join(INCLUDE, "kbatch.h")]
 

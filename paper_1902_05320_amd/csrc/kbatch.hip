@@ -29,6 +29,7 @@
 // another one may overwrite.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -54,13 +55,13 @@ constexpr int kScatterTile = 4096;  // messages per scatter workgroup
 
 // control words (uint32 indices into the ctl area)
 enum : int {
-  CTL_QUEUE = 0,     // uint64 (words 0, 1): items taken from the front | from the back << 32
   CTL_NITEMS = 2,    // number of queue items
   CTL_IDENTITY = 3,  // 1: arrival order kept, order[] unused
   CTL_MAXKEY = 4,    // largest block-count key seen
   CTL_ID_PER = 5,    // arrival order: messages per queue item
   CTL_USEFUL = 6,    // uint64 (words 6, 7): sum of (clamped) block counts
   CTL_IDLE = 8,      // uint64 (words 8, 9): lane-slots arrival-order waves would idle
+  CTL_PRIO_KEY = 10, // front waves raise their priority on items of at least this many blocks
   CTL_WORDS = 64
 };
 
@@ -68,6 +69,14 @@ enum : int {
 // (XCC, shader engine, shader array, CU, SIMD); the first wave to claim its
 // SIMD's flag takes queue items from the front.
 constexpr uint32_t kSimdSlots = 8 * 8 * 2 * 16 * 4;
+
+// The queue is dealt round-robin into kQueues sub-queues (item t goes to
+// sub-queue t mod kQueues, so each keeps the longest-first order); a wave
+// starts on the sub-queue of its XCD.  Each sub-queue is one uint64 counter
+// (items taken from the front | taken from the back << 32) on its own
+// 256-byte line.
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kQueueStrideDw = 64;
 
 struct WorkItem {
   uint32_t begin, end;  // positions in order[] (message indices in arrival order)
@@ -101,8 +110,7 @@ __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
                                              const uint64_t* __restrict__ offs,
                                              const uint64_t* __restrict__ lens,
                                              const uint8_t* __restrict__ vars, uint64_t i,
-                                             uint8_t* __restrict__ out, uint32_t* wave_lds,
-                                             uint32_t lane) {
+                                             uint8_t* __restrict__ out, uint32_t* row) {
   int var = V;
   if constexpr (V == kMixed) var = vars[i];
   uint8_t* o = out + i * static_cast<uint64_t>(out_stride<V>());
@@ -113,7 +121,7 @@ __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
     return;
   }
   Lane A[25];
-  kb::sponge_hash<V>(A, data + offs[i], lens[i], var, wave_lds, lane);
+  kb::sponge_hash<V>(A, data + offs[i], lens[i], var, row);
   kb::store_digest<V>(o, A, var);
 }
 
@@ -132,12 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_plain(const uint8_t* __restrict__ da
                                                   uint64_t first, uint64_t count,
                                                   uint8_t* __restrict__ out) {
   using S = SpongeShape<V>;
-  __shared__ __align__(16) uint32_t lds[(kBlock / 64) * S::kWaveDw];
-  uint32_t* wave_lds = lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::kWaveDw;
+  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
   const uint64_t p = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (p >= count) return;
   const uint64_t i = order ? order[first + p] : first + p;
-  hash_message<V>(data, offs, lens, vars, i, out, wave_lds, threadIdx.x & 63u);
+  hash_message<V>(data, offs, lens, vars, i, out, lds + threadIdx.x * S::kRowDw);
 }
 
 // Persistent form: waves pop queue items until the queue is drained.  Every
@@ -157,43 +164,73 @@ __device__ __forceinline__ uint32_t simd_slot() {
 
 // Persistent form.  Queue items are ordered longest first.  On each SIMD one
 // wave (the first to claim the SIMD's flag) takes items from the front at
-// raised issue priority, so the long absorb chains that bound the makespan
-// run back to back at full rate; the other resident waves take the shortest
-// items from the back and fill the issue slots the front wave leaves idle.
-// Both ends advance one packed 64-bit counter, so no item is taken twice, and
-// every wave leaves once the two ends meet, so the grid always drains.  In
-// arrival order (uniform work) every wave takes from the front at normal
-// priority.
+// raised issue priority while they are long, so the long absorb chains that
+// bound the makespan run back to back at full rate; the other resident waves
+// take the shortest items from the back and fill the issue slots the front
+// wave leaves idle.  Both ends of a sub-queue advance one packed 64-bit
+// counter, so no item is taken twice.  A wave drains the sub-queue of its own
+// XCD first and then the others in turn, so every item is taken whatever the
+// mapping of waves to XCDs, and every wave leaves once all sub-queues are
+// empty, so the grid always drains.  In arrival order (uniform work) every
+// wave takes from the front at normal priority.
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_persistent(
     const uint8_t* __restrict__ data, const uint64_t* __restrict__ offs,
     const uint64_t* __restrict__ lens, const uint8_t* __restrict__ vars,
     const uint32_t* __restrict__ order, const WorkItem* __restrict__ items,
-    uint32_t* __restrict__ ctl, uint32_t* __restrict__ simd_flags, uint8_t* __restrict__ out) {
+    const uint32_t* __restrict__ ctl, unsigned long long* __restrict__ queues,
+    uint32_t* __restrict__ simd_flags, uint8_t* __restrict__ out) {
   using S = SpongeShape<V>;
-  __shared__ __align__(16) uint32_t lds[(kBlock / 64) * S::kWaveDw];
-  uint32_t* wave_lds = lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::kWaveDw;
+  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
+  uint32_t* row = lds + threadIdx.x * S::kRowDw;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t n_items = ctl[CTL_NITEMS];
   const bool sorted = ctl[CTL_IDENTITY] == 0u;
+  const uint32_t prio_key = ctl[CTL_PRIO_KEY];
   const uint32_t* ord = sorted ? order : nullptr;
   uint32_t claim = 0;
   if (sorted && lane == 0) claim = atomicCAS(&simd_flags[simd_slot()], 0u, 1u) == 0u ? 1u : 0u;
   const bool front = !sorted || __builtin_amdgcn_readfirstlane(__shfl(claim, 0)) != 0u;
-  if (sorted && front) __builtin_amdgcn_s_setprio(3);
-  unsigned long long* queue = reinterpret_cast<unsigned long long*>(&ctl[CTL_QUEUE]);
-  const unsigned long long step = front ? 1ull : (1ull << 32);
+  const unsigned long long step = 1ull << (front ? 0 : 32);
+  const uint32_t home = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kQueues - 1u);
+  uint32_t qi = 0;  // sub-queues tried so far (bucketed order)
   for (;;) {
-    unsigned long long old = 0;
-    if (lane == 0) old = __hip_atomic_fetch_add(queue, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t head = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old), 0));
-    const uint32_t tail = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old >> 32), 0));
-    if (static_cast<uint64_t>(head) + tail >= n_items) break;
-    const uint32_t t = front ? head : n_items - 1u - tail;
+    // choose the next item; the hashing below appears once in the kernel
+    uint32_t t = 0xFFFFFFFFu;
+    if (!sorted) {
+      uint32_t d = 0;
+      if (lane == 0)
+        d = __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(queues), 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+      d = __builtin_amdgcn_readfirstlane(__shfl(d, 0));
+      if (d < n_items) t = d;
+    } else {
+      while (qi < kQueues) {
+        const uint32_t x = (home + qi) & (kQueues - 1u);
+        const uint32_t m = n_items > x ? (n_items - x + kQueues - 1u) / kQueues : 0u;
+        unsigned long long old = 0;
+        if (lane == 0)
+          old = __hip_atomic_fetch_add(queues + x * (kQueueStrideDw / 2), step, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t head = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old), 0));
+        const uint32_t tail =
+            __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old >> 32), 0));
+        if (static_cast<uint64_t>(head) + tail < m) {
+          t = x + kQueues * (front ? head : m - 1u - tail);
+          break;
+        }
+        ++qi;
+      }
+    }
+    if (t == 0xFFFFFFFFu) break;
     const WorkItem it = items[t];
+    if (sorted && front && it.key >= prio_key)
+      __builtin_amdgcn_s_setprio(3);
+    else
+      __builtin_amdgcn_s_setprio(0);
     for (uint32_t pos = it.begin + lane; pos < it.end; pos += 64u) {
       const uint64_t i = ord ? ord[pos] : pos;
-      hash_message<V>(data, offs, lens, vars, i, out, wave_lds, lane);
+      hash_message<V>(data, offs, lens, vars, i, out, row);
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -218,9 +255,8 @@ __global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ dat
                                                  int first, int levels, TreeLevels lv) {
   using S = SpongeShape<V>;
   constexpr uint64_t D = kb::digest_bytes_of(V);
-  __shared__ __align__(16) uint32_t lds[(kBlock / 64) * S::kWaveDw];
-  uint32_t* wave_lds = lds + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * S::kWaveDw;
-  const uint32_t lane = threadIdx.x & 63u;
+  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
+  uint32_t* row = lds + threadIdx.x * S::kRowDw;
   const uint64_t w = blockIdx.x;
   if (first == 0) {
     const uint64_t i = w * kBlock + threadIdx.x;
@@ -228,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ dat
       const uint64_t off = i * leaf_size;
       const uint64_t len = total - off < leaf_size ? total - off : leaf_size;
       Lane A[25];
-      kb::sponge_hash<V>(A, data + off, len, V, wave_lds, lane);
+      kb::sponge_hash<V>(A, data + off, len, V, row);
       kb::store_digest<V>(nodes + lv.off[0] + i * D, A, V);
     }
   }
@@ -242,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ dat
       uint8_t* dst = nodes + lv.off[l + 1] + j * D;
       if (2 * j + 1 < lv.m[l]) {
         Lane A[25];
-        kb::sponge_hash<V>(A, src, 2 * D, V, wave_lds, lane);
+        kb::sponge_hash<V>(A, src, 2 * D, V, row);
         kb::store_digest<V>(dst, A, V);
       } else {
         const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
@@ -398,7 +434,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
     ctl[CTL_IDENTITY] = identity;
     if (identity) {
       const uint64_t avg = useful / (n ? n : 1);
-      const uint32_t per = item_msgs(avg > 0xFFFFu ? 0xFFFFu : static_cast<uint32_t>(avg), steps);
+      const uint32_t per = item_msgs(avg > 0xFFFFu ? 0xFFFFu : static_cast<uint32_t>(avg), 8u);
       ctl[CTL_ID_PER] = per;
       ctl[CTL_NITEMS] = static_cast<uint32_t>((n + per - 1) / per);
     }
@@ -423,7 +459,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restric
     it_run += items[q];
     iend[4u * t + q] = it_run;
   }
-  if (t == kPlanThreads - 1) ctl[CTL_NITEMS] = it_run;
+  if (t == kPlanThreads - 1) {
+    ctl[CTL_NITEMS] = it_run;
+    const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
+    const uint64_t avg = useful / (n ? n : 1);
+    ctl[CTL_PRIO_KEY] = static_cast<uint32_t>(2u * avg + 2u);
+  }
 }
 
 // Queue item t: its bucket (the smallest rank r with iend[r] > t) and its
@@ -498,6 +539,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__
   }
 }
 
+// Count the dwords where two digest buffers differ (autotuner parity gate).
+__global__ __launch_bounds__(kBlock) void k_compare(const uint32_t* __restrict__ a,
+                                                    const uint32_t* __restrict__ b, uint64_t words,
+                                                    unsigned long long* __restrict__ mismatches) {
+  unsigned long long c = 0;
+  for (uint64_t k = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; k < words;
+       k += static_cast<uint64_t>(gridDim.x) * kBlock)
+    c += a[k] != b[k];
+  if (c) atomicAdd(mismatches, c);
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -521,7 +573,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 struct Workspace {
-  uint32_t* meta = nullptr;  // hist | start | cursor | iend | ctl | simd flags
+  uint32_t* meta = nullptr;  // hist | start | cursor | iend | ctl | sub-queues | simd flags
   uint32_t* order = nullptr;
   uint64_t order_cap = 0;
   WorkItem* items = nullptr;
@@ -531,7 +583,7 @@ struct Workspace {
   uint32_t* host_hist = nullptr;  // pinned, for the per-bucket form
 };
 
-constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS + kSimdSlots;
+constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS + kQueues * kQueueStrideDw + kSimdSlots;
 
 // Measurement hook state (keccak_timing_*): event pairs around kernel launches.
 struct Timing {
@@ -549,6 +601,8 @@ struct TimedLaunch {
   explicit TimedLaunch(hipStream_t st) : s(st) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing.on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     if (g_timing.used == g_timing.pool.size()) {
       std::pair<hipEvent_t, hipEvent_t> e{nullptr, nullptr};
       if (hipEventCreate(&e.first) != hipSuccess || hipEventCreate(&e.second) != hipSuccess) {
@@ -692,13 +746,13 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, h
 }
 
 template <int V>
-int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s) {
+int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Workspace* own) {
   if (mode == KB_MODE_PLAIN) return launch_plain<V>(b, nullptr, 0, b.n, s);
   if (b.n >= 0xFFFFFFFFull) return launch_plain<V>(b, nullptr, 0, b.n, s);  // 32-bit order[]
-  Workspace* w = nullptr;
-  int rc = get_ws(s, b.n, 0, &w);
+  Workspace* w = own;
+  int rc = own ? KB_OK : get_ws(s, b.n, 0, &w);
   if (rc) return rc;
-  uint32_t steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 8u;
+  uint32_t steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 4u;
   if (mode == KB_MODE_PER_BUCKET) {
     rc = run_schedule<V>(b, *w, steps, 1, s);
     if (rc) return rc;
@@ -733,19 +787,21 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s) {
     TimedLaunch tl(s);
     hipLaunchKernelGGL(k_persistent<V>, dim3(grid), dim3(kBlock), 0, s, b.data, b.offs, b.lens,
                        b.vars, w->order, w->items, w->meta + 4 * kKeyBins,
-                       w->meta + 4 * kKeyBins + CTL_WORDS, b.out);
+                       reinterpret_cast<unsigned long long*>(w->meta + 4 * kKeyBins + CTL_WORDS),
+                       w->meta + 4 * kKeyBins + CTL_WORDS + kQueues * kQueueStrideDw, b.out);
   }
   KB_HIP(hipGetLastError());
   return KB_OK;
 }
 
-int dispatch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s) {
+// `own`: a caller-owned workspace (a captured graph's), else the stream's.
+int dispatch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Workspace* own = nullptr) {
   switch (b.variant) {
-    case 0: return run_batch<0>(b, mode, tile, s);
-    case 1: return run_batch<1>(b, mode, tile, s);
-    case 2: return run_batch<2>(b, mode, tile, s);
-    case 3: return run_batch<3>(b, mode, tile, s);
-    default: return run_batch<kMixed>(b, mode, tile, s);
+    case 0: return run_batch<0>(b, mode, tile, s, own);
+    case 1: return run_batch<1>(b, mode, tile, s, own);
+    case 2: return run_batch<2>(b, mode, tile, s, own);
+    case 3: return run_batch<3>(b, mode, tile, s, own);
+    default: return run_batch<kMixed>(b, mode, tile, s, own);
   }
 }
 
@@ -774,7 +830,8 @@ int batch_entry(int variant, const uint8_t* vars, const uint8_t* data, const uin
 }
 
 template <int V>
-int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* root, hipStream_t s) {
+int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* root, hipStream_t s,
+                Workspace* own) {
   constexpr uint64_t D = kb::digest_bytes_of(V);
   TreeLevels lv{};
   lv.m[0] = total ? (total + leaf - 1) / leaf : 1;
@@ -785,8 +842,8 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
     lv.off[L + 1] = lv.off[L] + lv.m[L] * D;
     ++L;
   }
-  Workspace* w = nullptr;
-  int rc = get_ws(s, 0, lv.off[L] + D, &w);
+  Workspace* w = own;
+  int rc = own ? KB_OK : get_ws(s, 0, lv.off[L] + D, &w);
   if (rc) return rc;
   int first = 0;
   do {
@@ -801,6 +858,76 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
     first += levels;
   } while (first < L);
   KB_HIP(hipMemcpyAsync(root, w->tree + lv.off[L], D, hipMemcpyDeviceToDevice, s));
+  return KB_OK;
+}
+
+// Median of a small vector (modifies it).
+double median(std::vector<double>& v) {
+  std::sort(v.begin(), v.end());
+  return v.empty() ? 0.0 : v[v.size() / 2];
+}
+
+struct GraphHolder {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct kb_graph {
+  GraphHolder h;
+  Workspace ws;  // private: captured kernels point into it
+};
+
+namespace {
+
+void free_ws(Workspace& w) {
+  if (w.meta) (void)hipFree(w.meta);
+  if (w.order) (void)hipFree(w.order);
+  if (w.items) (void)hipFree(w.items);
+  if (w.tree) (void)hipFree(w.tree);
+  if (w.host_hist) (void)hipHostFree(w.host_hist);
+  w = Workspace{};
+}
+
+// Size a graph's private workspace for `msgs` messages and `tree_bytes`.
+int size_ws(Workspace& w, uint64_t msgs, uint64_t tree_bytes, hipStream_t s) {
+  uint64_t cap = 0;
+  int rc = grow(reinterpret_cast<void**>(&w.meta), &cap, kMetaWords * 4ull, s);
+  if (!rc && msgs) rc = grow(reinterpret_cast<void**>(&w.order), &w.order_cap, msgs * 4ull, s);
+  if (!rc && msgs)
+    rc = grow(reinterpret_cast<void**>(&w.items), &w.items_cap, max_items(msgs) * sizeof(WorkItem), s);
+  if (!rc && tree_bytes) rc = grow(reinterpret_cast<void**>(&w.tree), &w.tree_cap, tree_bytes, s);
+  return rc;
+}
+
+// Capture whatever `enqueue` puts on `stream` into a graph that owns `g`.
+template <class F>
+int capture(hipStream_t stream, F&& enqueue, kb_graph* g, kb_graph** out) {
+  const hipError_t eb = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) {
+    free_ws(g->ws);
+    delete g;
+    return fail(KB_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(eb));
+  }
+  int rc = enqueue();
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(stream, &graph);
+  hipGraphExec_t exec = nullptr;
+  if (rc == KB_OK && e != hipSuccess) rc = fail(KB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  if (rc == KB_OK) {
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e2 != hipSuccess) rc = fail(KB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  }
+  if (rc != KB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    free_ws(g->ws);
+    delete g;
+    return rc;
+  }
+  g->h.graph = graph;
+  g->h.exec = exec;
+  *out = g;
   return KB_OK;
 }
 
@@ -843,11 +970,185 @@ int merkle_root(int variant, const uint8_t* d_data, uint64_t total_len, uint64_t
   if (leaf_size == 0) return fail(KB_EINVAL, "leaf_size must be positive");
   if (!d_root || (total_len && !d_data)) return fail(KB_EINVAL, "NULL pointer");
   switch (variant) {
-    case 0: return merkle_impl<0>(d_data, total_len, leaf_size, d_root, stream);
-    case 1: return merkle_impl<1>(d_data, total_len, leaf_size, d_root, stream);
-    case 2: return merkle_impl<2>(d_data, total_len, leaf_size, d_root, stream);
-    default: return merkle_impl<3>(d_data, total_len, leaf_size, d_root, stream);
+    case 0: return merkle_impl<0>(d_data, total_len, leaf_size, d_root, stream, nullptr);
+    case 1: return merkle_impl<1>(d_data, total_len, leaf_size, d_root, stream, nullptr);
+    case 2: return merkle_impl<2>(d_data, total_len, leaf_size, d_root, stream, nullptr);
+    default: return merkle_impl<3>(d_data, total_len, leaf_size, d_root, stream, nullptr);
   }
+}
+
+int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_data,
+                    const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n, int reps,
+                    kb_tile* best, double* best_ms, int* rejected, hipStream_t stream) {
+  g_err.clear();
+  if (!best || !best_ms || !rejected) return fail(KB_EINVAL, "NULL output pointer");
+  if (variant != -1 && (variant < 0 || variant > 3))
+    return fail(KB_EINVAL, "variant %d is neither -1 (mixed) nor a SHA-3 variant", variant);
+  const int v = variant == -1 ? kMixed : variant;
+  Batch b{v, d_variants, d_data, d_offsets, d_lengths, n, nullptr};
+  int rc = check_batch(Batch{v, d_variants, d_data, d_offsets, d_lengths, n,
+                             reinterpret_cast<uint8_t*>(uintptr_t{256})},
+                       KB_MODE_PERSISTENT);
+  if (rc) return rc;
+  if (n == 0) return fail(KB_EINVAL, "nothing to tune on an empty batch");
+  if (reps < 1) reps = 1;
+  const uint64_t bytes = n * static_cast<uint64_t>(v == kMixed ? 64 : kb::digest_bytes_of(v));
+  uint8_t *ref = nullptr, *cand = nullptr;
+  unsigned long long* mism = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (ref) (void)hipFree(ref);
+    if (cand) (void)hipFree(cand);
+    if (mism) (void)hipFree(mism);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&ref, bytes) != hipSuccess || hipMalloc(&cand, bytes) != hipSuccess ||
+      hipMalloc(&mism, sizeof(unsigned long long)) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(KB_ENOMEM, "autotune could not allocate %llu bytes", 2ull * bytes);
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(KB_EHIP, "hipEventCreate failed");
+  }
+  b.out = ref;
+  rc = dispatch(b, KB_MODE_PLAIN, nullptr, stream);
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  const int steps_c[] = {1, 2, 4, 8, 16, 32};
+  const int waves_c[] = {1, 2, 0};  // 0 = occupancy maximum
+  double best_t = -1.0;
+  int nrej = 0;
+  for (int sp : steps_c)
+    for (int wv : waves_c) {
+      kb_tile t{};
+      t.steps_per_item = sp;
+      t.waves_per_simd = wv;
+      b.out = cand;
+      // parity gate: the candidate's digests must equal the plain form's
+      if (hipMemsetAsync(cand, 0xA5, bytes, stream) != hipSuccess ||
+          hipMemsetAsync(mism, 0, sizeof(unsigned long long), stream) != hipSuccess) {
+        cleanup();
+        return fail(KB_EHIP, "hipMemsetAsync failed");
+      }
+      rc = dispatch(b, KB_MODE_PERSISTENT, &t, stream);
+      if (rc) {
+        cleanup();
+        return rc;
+      }
+      hipLaunchKernelGGL(k_compare, dim3(1024), dim3(kBlock), 0, stream,
+                         reinterpret_cast<const uint32_t*>(ref), reinterpret_cast<const uint32_t*>(cand),
+                         bytes / 4, mism);
+      unsigned long long bad = 0;
+      if (hipMemcpyAsync(&bad, mism, sizeof bad, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        cleanup();
+        return fail(KB_EHIP, "autotune parity check failed to run");
+      }
+      if (bad) {
+        ++nrej;
+        continue;
+      }
+      std::vector<double> ts;
+      for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(e0, stream);
+        rc = dispatch(b, KB_MODE_PERSISTENT, &t, stream);
+        (void)hipEventRecord(e1, stream);
+        if (rc || hipEventSynchronize(e1) != hipSuccess) {
+          cleanup();
+          return rc ? rc : fail(KB_EHIP, "autotune timing failed");
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ts.push_back(ms);
+      }
+      const double tm = median(ts);
+      if (best_t < 0.0 || tm < best_t) {
+        best_t = tm;
+        *best = t;
+      }
+    }
+  cleanup();
+  *rejected = nrej;
+  if (best_t < 0.0) return fail(KB_EHIP, "every autotune candidate failed its parity check");
+  *best_ms = best_t;
+  return KB_OK;
+}
+
+int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d_data,
+                        const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n,
+                        uint8_t* d_digests, int mode, const kb_tile* tile, hipStream_t stream,
+                        kb_graph** out) {
+  g_err.clear();
+  if (!out) return fail(KB_EINVAL, "NULL output pointer");
+  if (variant != -1 && (variant < 0 || variant > 3))
+    return fail(KB_EINVAL, "variant %d is neither -1 (mixed) nor a SHA-3 variant", variant);
+  if (mode != KB_MODE_PERSISTENT && mode != KB_MODE_PLAIN)
+    return fail(KB_EINVAL, "only the persistent and plain modes can be captured");
+  const int v = variant == -1 ? kMixed : variant;
+  Batch b{v, d_variants, d_data, d_offsets, d_lengths, n, d_digests};
+  int rc = check_batch(b, mode);
+  if (rc) return rc;
+  kb_graph* g = new kb_graph();
+  if (n && mode == KB_MODE_PERSISTENT) {
+    // everything the capture needs is allocated and looked up first
+    int dev = 0, cus = 0;
+    rc = hipGetDevice(&dev) == hipSuccess ? cu_count(dev, &cus) : fail(KB_EHIP, "hipGetDevice failed");
+    if (!rc) rc = size_ws(g->ws, n, 0, stream);
+    if (rc) {
+      free_ws(g->ws);
+      delete g;
+      return rc;
+    }
+  }
+  return capture(stream, [&]() { return n ? dispatch(b, mode, tile, stream, &g->ws) : KB_OK; }, g, out);
+}
+
+int keccak_graph_create_merkle(int variant, const uint8_t* d_data, uint64_t total_len,
+                               uint64_t leaf_size, uint8_t* d_root, hipStream_t stream,
+                               kb_graph** out) {
+  g_err.clear();
+  if (!out) return fail(KB_EINVAL, "NULL output pointer");
+  if (variant < 0 || variant > 3) return fail(KB_EINVAL, "variant %d is not a SHA-3 variant", variant);
+  if (leaf_size == 0) return fail(KB_EINVAL, "leaf_size must be positive");
+  if (!d_root || (total_len && !d_data)) return fail(KB_EINVAL, "NULL pointer");
+  const uint64_t leaves = total_len ? (total_len + leaf_size - 1) / leaf_size : 1;
+  kb_graph* g = new kb_graph();
+  const int rc = size_ws(g->ws, 0, (2 * leaves + 1) * 64ull, stream);
+  if (rc) {
+    free_ws(g->ws);
+    delete g;
+    return rc;
+  }
+  return capture(stream, [&]() {
+        switch (variant) {
+          case 0: return merkle_impl<0>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
+          case 1: return merkle_impl<1>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
+          case 2: return merkle_impl<2>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
+          default: return merkle_impl<3>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
+        }
+      }, g, out);
+}
+
+int keccak_graph_launch(kb_graph* graph, hipStream_t stream) {
+  g_err.clear();
+  if (!graph) return fail(KB_EINVAL, "NULL graph");
+  KB_HIP(hipGraphLaunch(graph->h.exec, stream));
+  return KB_OK;
+}
+
+int keccak_graph_destroy(kb_graph* graph) {
+  g_err.clear();
+  if (!graph) return KB_OK;
+  if (graph->h.exec) (void)hipGraphExecDestroy(graph->h.exec);
+  if (graph->h.graph) (void)hipGraphDestroy(graph->h.graph);
+  free_ws(graph->ws);
+  delete graph;
+  return KB_OK;
 }
 
 int keccak_digest_bytes(int variant) {

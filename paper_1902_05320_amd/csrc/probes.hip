@@ -13,13 +13,19 @@ namespace {
 constexpr int kProbeBlock = 256;
 constexpr int kChains = 16;  // independent dependency chains per thread
 
-// Each iteration issues kChains v_bitop3 (3-input xor) with no memory access.
+// Each iteration issues kChains independent v_bitop3 (each chain depends
+// only on itself), so with enough resident waves the SIMDs issue at their
+// logic-op rate; no memory is touched inside the loop.
 __global__ __launch_bounds__(kProbeBlock) void k_valu_probe(uint32_t iters, uint32_t seed,
                                                             uint32_t* __restrict__ sink,
                                                             uint64_t* __restrict__ clocks) {
-  uint32_t a[kChains];
+  uint32_t a[kChains], k1[kChains], k2[kChains];
 #pragma unroll
-  for (int j = 0; j < kChains; ++j) a[j] = seed + threadIdx.x * 7u + j;
+  for (int j = 0; j < kChains; ++j) {
+    a[j] = seed + threadIdx.x * 7u + j;
+    k1[j] = threadIdx.x * 5u + j;
+    k2[j] = threadIdx.x ^ (11u * j);
+  }
   const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
   uint64_t c0 = 0, w0 = 0;
   if (timer) {
@@ -28,8 +34,7 @@ __global__ __launch_bounds__(kProbeBlock) void k_valu_probe(uint32_t iters, uint
   }
   for (uint32_t it = 0; it < iters; ++it) {
 #pragma unroll
-    for (int j = 0; j < kChains; ++j)
-      a[j] = __builtin_amdgcn_bitop3_b32(a[j], a[(j + 1) % kChains], it, 0x96);
+    for (int j = 0; j < kChains; ++j) a[j] = __builtin_amdgcn_bitop3_b32(a[j], k1[j], k2[j], 0xd2);
   }
   uint32_t r = 0;
 #pragma unroll

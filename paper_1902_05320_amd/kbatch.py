@@ -29,6 +29,10 @@ KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
 # the C ABI entry points, in include/kbatch.h order
 EXPORTS = (
     "keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
+    "keccak_autotune", "keccak_graph_create", "keccak_graph_create_merkle",
+    "keccak_graph_launch", "keccak_graph_destroy",
+    "keccak_server_create", "keccak_server_submit", "keccak_server_poll", "keccak_server_result",
+    "keccak_server_stats", "keccak_server_destroy", "keccak_server_last_error",
     "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
     "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_copy",
     "keccak_last_error", "keccak_version",
@@ -44,6 +48,26 @@ class KbError(RuntimeError):
 class Tile(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
                 ("steps_per_item", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+EXECUTOR = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8),
+                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                            ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint8))
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("d_pool", ctypes.c_void_p), ("pool_bytes", ctypes.c_uint64),
+                ("max_step_msgs", ctypes.c_uint64), ("steps_in_flight", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("executor", EXECUTOR),
+                ("executor_user", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("messages", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+                ("max_step_msgs_seen", ctypes.c_uint64), ("step_busy_s", ctypes.c_double),
+                ("span_s", ctypes.c_double)]
 
 
 _lib = None
@@ -73,6 +97,23 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_probe_valu.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), vp]
     lib.keccak_probe_copy.argtypes = [vp, vp, u64, ctypes.POINTER(ctypes.c_double), vp]
+    lib.keccak_autotune.argtypes = [i32, vp, vp, vp, vp, u64, i32, ctypes.POINTER(Tile),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                    vp]
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.keccak_graph_create.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile),
+                                        vp, pp]
+    lib.keccak_graph_create_merkle.argtypes = [i32, vp, u64, u64, vp, vp, pp]
+    lib.keccak_graph_launch.argtypes = [vp, vp]
+    lib.keccak_graph_destroy.argtypes = [vp]
+    lib.keccak_server_create.argtypes = [ctypes.POINTER(ServerConfig), pp]
+    lib.keccak_server_submit.argtypes = [vp, i32, vp, vp, u64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.keccak_server_poll.argtypes = [vp, vp, u64, ctypes.POINTER(ctypes.c_uint64), i32]
+    lib.keccak_server_result.argtypes = [vp, u64, vp, u64, ctypes.POINTER(ctypes.c_double)]
+    lib.keccak_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.keccak_server_destroy.argtypes = [vp]
+    lib.keccak_server_last_error.argtypes = []
+    lib.keccak_server_last_error.restype = ctypes.c_char_p
     lib.keccak_last_error.argtypes = []
     lib.keccak_last_error.restype = ctypes.c_char_p
     lib.keccak_version.argtypes = []
@@ -80,7 +121,10 @@ def load_library(path: str = LIB_PATH):
     for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
               "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu",
-              "keccak_probe_copy"):
+              "keccak_probe_copy", "keccak_autotune", "keccak_graph_create",
+              "keccak_graph_create_merkle", "keccak_graph_launch", "keccak_graph_destroy",
+              "keccak_server_create", "keccak_server_submit", "keccak_server_poll",
+              "keccak_server_result", "keccak_server_stats", "keccak_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -228,6 +272,170 @@ def merkle_root(variant, data: torch.Tensor, leaf_size: int, out: torch.Tensor |
                          _stream_handle(stream))
     _check(rc)
     return out
+
+
+def autotune(variant, data: torch.Tensor, offsets: torch.Tensor, lengths: torch.Tensor,
+             variants: torch.Tensor | None = None, reps: int = 3, stream=None):
+    """Pick the persistent-form tile for this batch.  variant=-1 with
+    `variants` tunes the mixed form.  Returns (Tile, ms, rejected)."""
+    _require_gpu()
+    lib = load_library()
+    v = -1 if variant == -1 else variant_id(variant)
+    n = offsets.numel()
+    data = data.contiguous()
+    offsets = _as_u64_view(offsets, "offsets")
+    lengths = _as_u64_view(lengths, "lengths", n)
+    _check_bounds(data, offsets, lengths)
+    best, ms, rej = Tile(), ctypes.c_double(0.0), ctypes.c_int(0)
+    _check(lib.keccak_autotune(v, _ptr(variants), _ptr(data), _ptr(offsets), _ptr(lengths), n,
+                               int(reps), ctypes.byref(best), ctypes.byref(ms), ctypes.byref(rej),
+                               _stream_handle(stream)))
+    return best, ms.value, rej.value
+
+
+class Graph:
+    """A captured batch or tree; replay() enqueues it with one launch.  The
+    tensors it was created from must stay alive and in place."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def replay(self, stream=None):
+        _check(load_library().keccak_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if self._h:
+            load_library().keccak_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def graph_batch(variant, data, offsets, lengths, out, variants=None, mode="persistent",
+                tile: Tile | None = None, stream=None) -> Graph:
+    _require_gpu()
+    lib = load_library()
+    v = -1 if variant == -1 else variant_id(variant)
+    n = offsets.numel()
+    offsets = _as_u64_view(offsets, "offsets")
+    lengths = _as_u64_view(lengths, "lengths", n)
+    _check_bounds(data, offsets, lengths)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    h = ctypes.c_void_p(0)
+    _check(lib.keccak_graph_create(v, _ptr(variants), _ptr(data), _ptr(offsets), _ptr(lengths),
+                                   n, _ptr(out), m,
+                                   ctypes.byref(tile) if tile is not None else None,
+                                   _stream_handle(stream), ctypes.byref(h)))
+    return Graph(h, (data, offsets, lengths, out, variants))
+
+
+def graph_merkle(variant, data, leaf_size: int, out, stream=None) -> Graph:
+    _require_gpu()
+    lib = load_library()
+    h = ctypes.c_void_p(0)
+    _check(lib.keccak_graph_create_merkle(variant_id(variant), _ptr(data), data.numel(),
+                                          int(leaf_size), _ptr(out), _stream_handle(stream),
+                                          ctypes.byref(h)))
+    return Graph(h, (data, out))
+
+
+class Server:
+    """Continuous-batching hash server over a device byte pool (see
+    include/kbatch.h).  With `executor` (a Python callable taking numpy
+    arrays variants, offsets, lengths and returning uint8[n, 64]) the server
+    runs without a GPU."""
+
+    def __init__(self, pool: torch.Tensor | None, max_step_msgs: int = 1 << 16,
+                 steps_in_flight: int = 2, executor=None, pool_bytes: int | None = None):
+        import numpy as np
+        lib = load_library()
+        self._np = np
+        self._cb = None
+        cfg = ServerConfig()
+        if executor is None:
+            _require_gpu()
+            if pool is None or pool.dtype != torch.uint8 or not pool.is_cuda:
+                raise TypeError("pool must be a uint8 device tensor")
+            self._pool = pool.contiguous()
+            cfg.d_pool = _ptr(self._pool)
+            cfg.pool_bytes = self._pool.numel()
+        else:
+            self._pool = None
+            cfg.d_pool = None
+            cfg.pool_bytes = int(pool_bytes if pool_bytes is not None else 1 << 62)
+
+            def _run(user, var_p, off_p, len_p, n, out_p):
+                try:
+                    var = np.ctypeslib.as_array(var_p, shape=(n,)).copy()
+                    off = np.ctypeslib.as_array(off_p, shape=(n,)).copy()
+                    ln = np.ctypeslib.as_array(len_p, shape=(n,)).copy()
+                    res = np.ascontiguousarray(executor(var, off, ln), dtype=np.uint8)
+                    ctypes.memmove(out_p, res.ctypes.data, n * 64)
+                    return KB_OK
+                except Exception:  # reported to the server as a failed step
+                    return KB_EHIP
+
+            self._cb = EXECUTOR(_run)
+            cfg.executor = self._cb
+        cfg.max_step_msgs = int(max_step_msgs)
+        cfg.steps_in_flight = int(steps_in_flight)
+        h = ctypes.c_void_p(0)
+        rc = lib.keccak_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != KB_OK:
+            raise KbError(rc, lib.keccak_server_last_error().decode())
+        self._h = h
+
+    def _srv_check(self, rc):
+        if rc != KB_OK:
+            raise KbError(rc, load_library().keccak_server_last_error().decode())
+
+    def submit(self, variant, offsets, lengths) -> int:
+        np = self._np
+        offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+        lens = np.ascontiguousarray(lengths, dtype=np.uint64)
+        rid = ctypes.c_uint64(0)
+        self._srv_check(load_library().keccak_server_submit(
+            self._h, variant_id(variant), ctypes.c_void_p(offs.ctypes.data),
+            ctypes.c_void_p(lens.ctypes.data), offs.size, ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, max_ids: int = 4096, wait_ms: int = 0) -> list[int]:
+        np = self._np
+        ids = np.zeros(max_ids, dtype=np.uint64)
+        cnt = ctypes.c_uint64(0)
+        self._srv_check(load_library().keccak_server_poll(
+            self._h, ctypes.c_void_p(ids.ctypes.data), max_ids, ctypes.byref(cnt), int(wait_ms)))
+        return [int(x) for x in ids[:cnt.value]]
+
+    def result(self, rid: int, n: int):
+        """(uint8[n, 64] digests, latency ms) of a finished request."""
+        np = self._np
+        out = np.zeros((n, 64), dtype=np.uint8)
+        lat = ctypes.c_double(0.0)
+        self._srv_check(load_library().keccak_server_result(
+            self._h, rid, ctypes.c_void_p(out.ctypes.data), out.nbytes, ctypes.byref(lat)))
+        return out, lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._srv_check(load_library().keccak_server_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            load_library().keccak_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def reserve(max_msgs: int, max_leaves: int = 0, stream=None):

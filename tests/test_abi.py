@@ -14,6 +14,7 @@ HEADER = os.path.join(ROOT, "include", "kbatch.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = "\n".join(ln for ln in text.splitlines() if not ln.lstrip().startswith("typedef"))
     names = re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)
     return [n for n in names if not n.startswith("_")]
 

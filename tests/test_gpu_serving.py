@@ -1,0 +1,118 @@
+"""GPU: the serving engine (every request's digests equal the same request
+hashed alone, and the oracle), the autotuner's parity gate, and graph
+replays (each replay equals the eager result, with eager work in between)."""
+
+import numpy as np
+import pytest
+
+from paper_1902_05320_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_05320_amd import kbatch
+    kbatch.load_library()
+    return kbatch
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def test_server_results_equal_alone_and_oracle(kb, o2):
+    import torch
+    pool_np = wl.random_bytes(wl.rng_for(50), 1 << 24)
+    pool = torch.from_numpy(pool_np).cuda()
+    _say("server: 400 requests, steps of 4096 messages, 2 in flight")
+    srv = kb.Server(pool, max_step_msgs=4096, steps_in_flight=2)
+    rng = np.random.Generator(np.random.PCG64(51))
+    reqs = {}
+    for _ in range(400):
+        k = int(rng.integers(1, 300))
+        lens = wl.log_uniform_lengths(rng, k, 8192)
+        offs = rng.integers(0, pool_np.size - 8192, k)
+        var = int(rng.choice([1, 3]))
+        reqs[srv.submit(var, offs, lens)] = (var, offs, lens)
+    got = {}
+    while len(got) < len(reqs):
+        for rid in srv.poll(wait_ms=200):
+            got[rid] = srv.result(rid, reqs[rid][1].size)
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 400 and st["steps"] >= 2 and st["max_step_msgs_seen"] <= 4096
+    _say("server: compare with each request alone")
+    for i, (rid, (var, offs, lens)) in enumerate(reqs.items()):
+        o = torch.from_numpy(offs.astype(np.int64)).cuda()
+        ln = torch.from_numpy(lens.astype(np.int64)).cuda()
+        alone = kb.keccak_batch_mixed(torch.full((offs.size,), var, dtype=torch.uint8, device="cuda"),
+                                      pool, o, ln).cpu().numpy()
+        assert np.array_equal(got[rid][0], alone), rid
+        if i % 20 == 0:
+            want = o2.sha3_batch_mixed(np.full(offs.size, var, np.uint8), pool_np, offs, lens)
+            assert np.array_equal(alone, want), rid
+
+
+def test_autotune_candidates_pass_parity(kb, o2):
+    import torch
+    b = wl.uneven(30000, 6000, seed=52)
+    data = torch.from_numpy(b.data).cuda()
+    offs = torch.from_numpy(b.offsets).cuda()
+    lens = torch.from_numpy(b.lengths).cuda()
+    var = torch.from_numpy(b.variants).cuda()
+    _say("autotune mixed")
+    tile, ms, rejected = kb.autotune(-1, data, offs, lens, variants=var, reps=2)
+    assert rejected == 0 and ms > 0 and tile.steps_per_item >= 1
+    got = kb.keccak_batch_mixed(var, data, offs, lens, tile=tile).cpu().numpy()
+    assert np.array_equal(got, o2.sha3_batch_mixed(b.variants, b.data, b.offsets, b.lengths))
+    _say("autotune sha3_256")
+    tile, ms, rejected = kb.autotune(1, data, offs, lens, reps=2)
+    assert rejected == 0
+    got = kb.keccak_batch(1, data, offs, lens, tile=tile).cpu().numpy()
+    assert np.array_equal(got, o2.sha3_batch(256, b.data, b.offsets, b.lengths))
+
+
+@pytest.mark.parametrize("mode", ["persistent", "plain"])
+def test_graph_replays_equal_eager(kb, mode):
+    import torch
+    b = wl.uneven(20000, 5000, seed=53)
+    data = torch.from_numpy(b.data).cuda()
+    offs = torch.from_numpy(b.offsets).cuda()
+    lens = torch.from_numpy(b.lengths).cuda()
+    var = torch.from_numpy(b.variants).cuda()
+    eager = kb.keccak_batch_mixed(var, data, offs, lens, mode=mode)
+    out = torch.zeros((b.n, 64), dtype=torch.uint8, device="cuda")
+    _say("graph capture", mode)
+    g = kb.graph_batch(-1, data, offs, lens, out, variants=var, mode=mode)
+    for rep in range(4):
+        out.zero_()
+        # eager work between replays
+        other = kb.keccak_batch(1, data, offs[:1000].contiguous(), lens[:1000].contiguous())
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        del other
+    g.close()
+
+
+def test_merkle_graph_replays(kb, o2):
+    import torch
+    data_np = wl.merkle(3_000_001, seed=54)
+    data = torch.from_numpy(data_np).cuda()
+    want = o2.merkle_root(256, data_np, 4096)
+    root = torch.zeros(32, dtype=torch.uint8, device="cuda")
+    _say("merkle graph")
+    g = kb.graph_merkle(1, data, 4096, root)
+    for rep in range(3):
+        root.zero_()
+        kb.merkle_root(3, data, 1000)  # eager work on the same stream
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert root.cpu().numpy().tobytes() == want, rep
+    g.close()
