@@ -91,6 +91,20 @@ int keccak_batch_mixed(const uint8_t* d_variants, const uint8_t* d_data,
                        uint8_t* d_digests, hipStream_t stream);
 
 /*
+ * keccak_batch_xof -- SHAKE128 / SHAKE256 of n messages (Section 3.3, eqs.
+ * 17-18: Keccak[c = 2 * security] over M || 1111 with pad10*1), each
+ * squeezed to out_len bytes (Section 3.2: the output is read r bits at a
+ * time with the permutation applied between reads).
+ *   security   128 or 256.
+ *   out_len    output bytes per message (> 0 when n > 0).
+ *   d_out      uint8[n * out_len], output i at i * out_len (any alignment).
+ * Persistent, length-bucketed form.  Other arguments as keccak_batch.
+ */
+int keccak_batch_xof(int security, const uint8_t* d_data, const uint64_t* d_offsets,
+                     const uint64_t* d_lengths, uint64_t n, uint64_t out_len, uint8_t* d_out,
+                     hipStream_t stream);
+
+/*
  * keccak_batch_ex -- either form above with an explicit scheduling mode and
  * tile (tile may be NULL).  variant = -1 selects the mixed form (d_variants
  * required, 64-byte output slots); otherwise d_variants is ignored.

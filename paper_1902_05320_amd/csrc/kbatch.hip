@@ -43,6 +43,8 @@
 #include "sponge_device.h"
 
 using kb::kMixed;
+using kb::kShake128;
+using kb::kShake256;
 using kb::Lane;
 using kb::SpongeShape;
 
@@ -85,13 +87,8 @@ struct WorkItem {
 };
 
 template <int V>
-constexpr int out_stride() {
-  return V == kMixed ? 64 : kb::digest_bytes_of(V);
-}
-
-template <int V>
 __device__ __forceinline__ int rate_of(int var) {
-  return V == kMixed ? kb::rate_bytes_rt(var) : kb::rate_bytes_of(V);
+  return V == kMixed ? kb::rate_bytes_rt(var) : SpongeShape<V>::kMaxRate;
 }
 
 template <int V>
@@ -104,16 +101,24 @@ __device__ __forceinline__ uint32_t key_of(uint64_t nb) {
   return nb >= kKeyBins - 1 ? kKeyBins - 1 : static_cast<uint32_t>(nb);
 }
 
-// Hash message i into its output slot.
+// Hash message i into its output slot of `stride` bytes (the digest size,
+// 64 in the mixed form, the output length for the XOFs).
 template <int V>
 __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
                                              const uint64_t* __restrict__ offs,
                                              const uint64_t* __restrict__ lens,
                                              const uint8_t* __restrict__ vars, uint64_t i,
-                                             uint8_t* __restrict__ out, uint32_t* row) {
+                                             uint8_t* __restrict__ out, uint64_t stride,
+                                             uint32_t* row) {
   int var = V;
   if constexpr (V == kMixed) var = vars[i];
-  uint8_t* o = out + i * static_cast<uint64_t>(out_stride<V>());
+  uint8_t* o = out + i * stride;
+  if constexpr (V >= kShake128) {
+    Lane A[25];
+    kb::sponge_hash<V>(A, data + offs[i], lens[i], var, row);
+    kb::squeeze_xof<V>(A, o, stride);
+    return;
+  }
   if (V == kMixed && var > 3) {
     uint32_t* o32 = reinterpret_cast<uint32_t*>(o);
 #pragma unroll
@@ -138,13 +143,13 @@ __global__ __launch_bounds__(kBlock) void k_plain(const uint8_t* __restrict__ da
                                                   const uint8_t* __restrict__ vars,
                                                   const uint32_t* __restrict__ order,
                                                   uint64_t first, uint64_t count,
-                                                  uint8_t* __restrict__ out) {
+                                                  uint8_t* __restrict__ out, uint64_t stride) {
   using S = SpongeShape<V>;
   __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
   const uint64_t p = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (p >= count) return;
   const uint64_t i = order ? order[first + p] : first + p;
-  hash_message<V>(data, offs, lens, vars, i, out, lds + threadIdx.x * S::kRowDw);
+  hash_message<V>(data, offs, lens, vars, i, out, stride, lds + threadIdx.x * S::kRowDw);
 }
 
 // Persistent form: waves pop queue items until the queue is drained.  Every
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(
     const uint64_t* __restrict__ lens, const uint8_t* __restrict__ vars,
     const uint32_t* __restrict__ order, const WorkItem* __restrict__ items,
     const uint32_t* __restrict__ ctl, unsigned long long* __restrict__ queues,
-    uint32_t* __restrict__ simd_flags, uint8_t* __restrict__ out) {
+    uint32_t* __restrict__ simd_flags, uint8_t* __restrict__ out, uint64_t stride) {
   using S = SpongeShape<V>;
   __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
   uint32_t* row = lds + threadIdx.x * S::kRowDw;
@@ -230,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(
       __builtin_amdgcn_s_setprio(0);
     for (uint32_t pos = it.begin + lane; pos < it.end; pos += 64u) {
       const uint64_t i = ord ? ord[pos] : pos;
-      hash_message<V>(data, offs, lens, vars, i, out, row);
+      hash_message<V>(data, offs, lens, vars, i, out, stride, row);
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -687,14 +692,19 @@ int get_ws(hipStream_t stream, uint64_t msgs, uint64_t tree_bytes, Workspace** o
 }
 
 struct Batch {
-  int variant;  // 0..3, or kMixed
+  int variant;  // 0..3, kMixed, kShake128 or kShake256
   const uint8_t* vars;
   const uint8_t* data;
   const uint64_t* offs;
   const uint64_t* lens;
   uint64_t n;
   uint8_t* out;
+  uint64_t stride = 0;  // output bytes per message
 };
+
+uint64_t out_stride(int v) {
+  return v == kMixed ? 64u : static_cast<uint64_t>(kb::digest_bytes_of(v));
+}
 
 template <int V>
 int launch_plain(const Batch& b, const uint32_t* order, uint64_t first, uint64_t count,
@@ -705,7 +715,7 @@ int launch_plain(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
   {
     TimedLaunch tl(s);
     hipLaunchKernelGGL(k_plain<V>, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s,
-                       b.data, b.offs, b.lens, b.vars, order, first, count, b.out);
+                       b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
   }
   KB_HIP(hipGetLastError());
   return KB_OK;
@@ -788,7 +798,8 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Work
     hipLaunchKernelGGL(k_persistent<V>, dim3(grid), dim3(kBlock), 0, s, b.data, b.offs, b.lens,
                        b.vars, w->order, w->items, w->meta + 4 * kKeyBins,
                        reinterpret_cast<unsigned long long*>(w->meta + 4 * kKeyBins + CTL_WORDS),
-                       w->meta + 4 * kKeyBins + CTL_WORDS + kQueues * kQueueStrideDw, b.out);
+                       w->meta + 4 * kKeyBins + CTL_WORDS + kQueues * kQueueStrideDw, b.out,
+                       b.stride);
   }
   KB_HIP(hipGetLastError());
   return KB_OK;
@@ -801,12 +812,15 @@ int dispatch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Works
     case 1: return run_batch<1>(b, mode, tile, s, own);
     case 2: return run_batch<2>(b, mode, tile, s, own);
     case 3: return run_batch<3>(b, mode, tile, s, own);
+    case kShake128: return run_batch<kShake128>(b, mode, tile, s, own);
+    case kShake256: return run_batch<kShake256>(b, mode, tile, s, own);
     default: return run_batch<kMixed>(b, mode, tile, s, own);
   }
 }
 
 int check_batch(const Batch& b, int mode) {
-  if (b.variant != kMixed && (b.variant < 0 || b.variant > 3))
+  if (b.variant != kMixed && b.variant != kShake128 && b.variant != kShake256 &&
+      (b.variant < 0 || b.variant > 3))
     return fail(KB_EINVAL, "variant %d is not a SHA-3 variant (0..3)", b.variant);
   if (mode < KB_MODE_PERSISTENT || mode > KB_MODE_PER_BUCKET)
     return fail(KB_EINVAL, "unknown scheduling mode %d", mode);
@@ -815,7 +829,8 @@ int check_batch(const Batch& b, int mode) {
     return fail(KB_EINVAL, "NULL pointer with n > 0");
   if (reinterpret_cast<uintptr_t>(b.offs) % 8 || reinterpret_cast<uintptr_t>(b.lens) % 8)
     return fail(KB_EINVAL, "d_offsets and d_lengths must be 8-byte aligned");
-  if (reinterpret_cast<uintptr_t>(b.out) % 4) return fail(KB_EINVAL, "d_digests must be 4-byte aligned");
+  if (b.variant < kShake128 && reinterpret_cast<uintptr_t>(b.out) % 4)
+    return fail(KB_EINVAL, "d_digests must be 4-byte aligned");
   return KB_OK;
 }
 
@@ -823,7 +838,7 @@ int batch_entry(int variant, const uint8_t* vars, const uint8_t* data, const uin
                 const uint64_t* lens, uint64_t n, uint8_t* out, int mode, const kb_tile* tile,
                 hipStream_t s) {
   g_err.clear();
-  Batch b{variant, vars, data, offs, lens, n, out};
+  Batch b{variant, vars, data, offs, lens, n, out, out_stride(variant)};
   int rc = check_batch(b, mode);
   if (rc || n == 0) return rc;
   return dispatch(b, mode, tile, s);
@@ -945,6 +960,20 @@ int keccak_batch(int variant, const uint8_t* d_data, const uint64_t* d_offsets,
                      KB_MODE_PERSISTENT, nullptr, stream);
 }
 
+int keccak_batch_xof(int security, const uint8_t* d_data, const uint64_t* d_offsets,
+                     const uint64_t* d_lengths, uint64_t n, uint64_t out_len, uint8_t* d_out,
+                     hipStream_t stream) {
+  g_err.clear();
+  if (security != 128 && security != 256)
+    return fail(KB_EINVAL, "SHAKE security level must be 128 or 256, not %d", security);
+  if (n && out_len == 0) return fail(KB_EINVAL, "out_len must be positive");
+  Batch b{security == 128 ? kShake128 : kShake256, nullptr, d_data, d_offsets, d_lengths, n,
+          d_out, out_len};
+  int rc = check_batch(b, KB_MODE_PERSISTENT);
+  if (rc || n == 0) return rc;
+  return dispatch(b, KB_MODE_PERSISTENT, nullptr, stream);
+}
+
 int keccak_batch_mixed(const uint8_t* d_variants, const uint8_t* d_data,
                        const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n,
                        uint8_t* d_digests, hipStream_t stream) {
@@ -985,14 +1014,14 @@ int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_dat
   if (variant != -1 && (variant < 0 || variant > 3))
     return fail(KB_EINVAL, "variant %d is neither -1 (mixed) nor a SHA-3 variant", variant);
   const int v = variant == -1 ? kMixed : variant;
-  Batch b{v, d_variants, d_data, d_offsets, d_lengths, n, nullptr};
+  Batch b{v, d_variants, d_data, d_offsets, d_lengths, n, nullptr, out_stride(v)};
   int rc = check_batch(Batch{v, d_variants, d_data, d_offsets, d_lengths, n,
-                             reinterpret_cast<uint8_t*>(uintptr_t{256})},
+                             reinterpret_cast<uint8_t*>(uintptr_t{256}), 0},
                        KB_MODE_PERSISTENT);
   if (rc) return rc;
   if (n == 0) return fail(KB_EINVAL, "nothing to tune on an empty batch");
   if (reps < 1) reps = 1;
-  const uint64_t bytes = n * static_cast<uint64_t>(v == kMixed ? 64 : kb::digest_bytes_of(v));
+  const uint64_t bytes = n * out_stride(v);
   uint8_t *ref = nullptr, *cand = nullptr;
   unsigned long long* mism = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1090,7 +1119,7 @@ int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d
   if (mode != KB_MODE_PERSISTENT && mode != KB_MODE_PLAIN)
     return fail(KB_EINVAL, "only the persistent and plain modes can be captured");
   const int v = variant == -1 ? kMixed : variant;
-  Batch b{v, d_variants, d_data, d_offsets, d_lengths, n, d_digests};
+  Batch b{v, d_variants, d_data, d_offsets, d_lengths, n, d_digests, out_stride(v)};
   int rc = check_batch(b, mode);
   if (rc) return rc;
   kb_graph* g = new kb_graph();

@@ -7,15 +7,18 @@
 //      byte offset costs at most ceil((R + 15) / 16) vector loads;
 //   2. on the final block the bytes past the message end are cleared and the
 //      suffix/padding bytes are written with byte-granular LDS stores: 0x06
-//      (bits 0,1 of the suffix "01" then the first pad bit) at the message
-//      end, 0x80 (the last pad bit) on byte R-1, or 0x86 when both fall on
-//      byte R-1 -- the byte form of N || pad10*1 with j = (-m-2) mod r;
+//      (bits 0,1 of the suffix "01" then the first pad bit; 0x1F for the
+//      SHAKE suffix "1111") at the message end, 0x80 (the last pad bit) on
+//      byte R-1, or the two OR-ed when both fall on byte R-1 -- the byte form
+//      of N || pad10*1 with j = (-m-2) mod r;
 //   3. the row is read back as dwords and realigned with v_alignbyte.
 // The data-dependent byte positions thus cost LDS address arithmetic, not
 // per-dword VALU masking.
 //
-// Variant `V` is 0..3 (SHA3-224/256/384/512, rate fixed at compile time) or
-// kMixed (rate chosen per thread at run time).
+// Variant `V` is 0..3 (SHA3-224/256/384/512, rate fixed at compile time),
+// kMixed (one of those four chosen per thread at run time), or kShake128 /
+// kShake256 (the XOFs of eqs. 17-18: suffix 1111, so the byte after the
+// message is 0x1F, and any output length).
 #pragma once
 
 #include "keccak_device.h"
@@ -23,16 +26,22 @@
 namespace kb {
 
 constexpr int kMixed = 4;
+constexpr int kShake128 = 5;  // Keccak[256]: rate 168 bytes
+constexpr int kShake256 = 6;  // Keccak[512]: rate 136 bytes
 
 template <int V>
 struct SpongeShape {
-  static constexpr int kMaxRate = V == kMixed ? 144 : rate_bytes_of(V);
+  static constexpr int kMaxRate =
+      V == kMixed ? 144 : V == kShake128 ? 168 : V == kShake256 ? 136 : rate_bytes_of(V);
   static constexpr int kMaxRateDw = kMaxRate / 4;
   // 16-byte chunks that can hold R bytes starting at any offset mod 16
   static constexpr int kChunks = (kMaxRate + 15 + 15) / 16;
   // chunk area plus room for the padding stores past the last chunk
   static constexpr int kRowDw = kChunks * 4 + 4;
-  static constexpr int kMaxDigestDw = V == kMixed ? 16 : digest_bytes_of(V) / 4;
+  static constexpr int kMaxDigestDw = V == kMixed ? 16 : V >= kShake128 ? 0 : digest_bytes_of(V) / 4;
+  // the suffix bits and the first pad bit, as the byte after the message:
+  // SHA-3 "01" then 1 -> 0x06; SHAKE "1111" then 1 -> 0x1F
+  static constexpr uint32_t kPadByte = V >= kShake128 ? 0x1Fu : 0x06u;
 };
 
 __device__ __forceinline__ int rate_bytes_rt(int v) { return 200 - 2 * (v == 0 ? 28 : v == 1 ? 32 : v == 2 ? 48 : 64); }
@@ -71,10 +80,10 @@ __device__ __forceinline__ void stage_block(uint32_t* __restrict__ row, const ui
     row[d0 + 1] = 0u;
     row[d0 + 2] = 0u;
     uint8_t* rb = reinterpret_cast<uint8_t*>(row);
-    rb[nv] = 0x06u;
+    rb[nv] = S::kPadByte;
     rb[nv + 1] = 0u;
     rb[nv + 2] = 0u;
-    rb[s16 + R - 1] = rem + 1u == static_cast<uint32_t>(R) ? 0x86u : 0x80u;
+    rb[s16 + R - 1] = rem + 1u == static_cast<uint32_t>(R) ? (S::kPadByte | 0x80u) : 0x80u;
   }
   const uint32_t* src = row + (s16 >> 2);
   const uint32_t sh = s16 & 3u;
@@ -89,7 +98,7 @@ template <int V>
 __device__ __forceinline__ void sponge_hash(Lane (&A)[25], const uint8_t* msg, uint64_t len,
                                             int var, uint32_t* __restrict__ row) {
   using S = SpongeShape<V>;
-  const int R = V == kMixed ? rate_bytes_rt(var) : rate_bytes_of(V);
+  const int R = V == kMixed ? rate_bytes_rt(var) : S::kMaxRate;
   const int RW = R / 4;
   // blocks of the padded message: the 2 suffix bits and the pad fit after
   // any byte-aligned message, so nb = floor(L / R) + 1
@@ -121,9 +130,35 @@ __device__ __forceinline__ void sponge_hash(Lane (&A)[25], const uint8_t* msg, u
       }
     }
     keccak_rounds_0_22(A);
-    if (!fin) keccak_round(A, 23);
+    if (!fin || V >= kShake128) keccak_round(A, 23);
   }
-  keccak_round(A, 23);
+  if (V < kShake128) keccak_round(A, 23);
+}
+
+// XOF squeeze (Section 3.2: the output is read r bits at a time, applying
+// the permutation between reads, until out_len bytes are produced).  A holds
+// the state after the last absorbed block's permutation.  Bytes are stored
+// one by one unless out_len is a multiple of 4 and `out` is 4-byte aligned.
+template <int V>
+__device__ __forceinline__ void squeeze_xof(Lane (&A)[25], uint8_t* out, uint64_t out_len) {
+  constexpr int R = SpongeShape<V>::kMaxRate;
+  const bool words = (out_len & 3u) == 0 && (reinterpret_cast<uintptr_t>(out) & 3u) == 0;
+  for (uint64_t done = 0;;) {
+#pragma unroll
+    for (int k = 0; k < R / 4; ++k) {
+      const uint32_t v = (k & 1) ? A[k >> 1].hi : A[k >> 1].lo;
+      const uint64_t at = done + 4u * k;
+      if (at >= out_len) break;
+      if (words) {
+        *reinterpret_cast<uint32_t*>(out + at) = v;
+      } else {
+        for (int q = 0; q < 4 && at + q < out_len; ++q) out[at + q] = static_cast<uint8_t>(v >> (8 * q));
+      }
+    }
+    done += R;
+    if (done >= out_len) break;
+    keccak_f1600(A);
+  }
 }
 
 // Trunc_d of the squeezed state: the first D bytes are dwords 0..D/4-1 in

@@ -28,7 +28,7 @@ KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
 
 # the C ABI entry points, in include/kbatch.h order
 EXPORTS = (
-    "keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
+    "keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_ex", "merkle_root",
     "keccak_autotune", "keccak_graph_create", "keccak_graph_create_merkle",
     "keccak_graph_launch", "keccak_graph_destroy",
     "keccak_server_create", "keccak_server_submit", "keccak_server_poll", "keccak_server_result",
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_batch.argtypes = [i32, vp, vp, vp, u64, vp, vp]
     lib.keccak_batch_mixed.argtypes = [vp, vp, vp, vp, u64, vp, vp]
     lib.keccak_batch_ex.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile), vp]
+    lib.keccak_batch_xof.argtypes = [i32, vp, vp, vp, u64, u64, vp, vp]
     lib.merkle_root.argtypes = [i32, vp, u64, u64, vp, vp]
     lib.keccak_digest_bytes.argtypes = [i32]
     lib.keccak_rate_bytes.argtypes = [i32]
@@ -118,7 +119,8 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_last_error.restype = ctypes.c_char_p
     lib.keccak_version.argtypes = []
     lib.keccak_version.restype = ctypes.c_char_p
-    for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_ex", "merkle_root",
+    for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_ex",
+              "merkle_root",
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
               "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu",
               "keccak_probe_copy", "keccak_autotune", "keccak_graph_create",
@@ -251,6 +253,36 @@ def keccak_batch_mixed(variants: torch.Tensor, data: torch.Tensor, offsets: torc
                                  _ptr(out), m, ctypes.byref(tile) if tile is not None else None,
                                  _stream_handle(stream))
     _check(rc)
+    return out
+
+
+def keccak_batch_xof(security: int, data: torch.Tensor, offsets: torch.Tensor,
+                     lengths: torch.Tensor, out_len: int, out: torch.Tensor | None = None,
+                     stream=None, check_bounds: bool = True) -> torch.Tensor:
+    """SHAKE128/256 of every slice, out_len bytes each; returns uint8[n, out_len]."""
+    _require_gpu()
+    lib = load_library()
+    if security not in (128, 256):
+        raise ValueError("security must be 128 or 256")
+    n = offsets.numel()
+    if data.dtype != torch.uint8 or not data.is_cuda:
+        raise TypeError("data must be a uint8 device tensor")
+    data = data.contiguous()
+    offsets = _as_u64_view(offsets, "offsets")
+    lengths = _as_u64_view(lengths, "lengths", n)
+    if check_bounds:
+        _check_bounds(data, offsets, lengths)
+    if out_len <= 0:
+        raise ValueError("out_len must be positive")
+    if out is None:
+        out = torch.empty((n, out_len), dtype=torch.uint8, device=data.device)
+    elif out.dtype != torch.uint8 or out.numel() != n * out_len or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous uint8 tensor of {n * out_len} bytes")
+    if n == 0:
+        return out
+    dptr = _ptr(data) if data.numel() else ctypes.c_void_p(out.data_ptr())
+    _check(lib.keccak_batch_xof(security, dptr, _ptr(offsets), _ptr(lengths), n, int(out_len),
+                                _ptr(out), _stream_handle(stream)))
     return out
 
 

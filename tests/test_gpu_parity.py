@@ -227,3 +227,19 @@ def test_full_merkle_1gib(kb, o2):
     got = kb.merkle_root(1, d, 4096)
     torch.cuda.synchronize()
     assert got.cpu().numpy().tobytes() == o2.merkle_root(256, data, 4096)
+
+
+@pytest.mark.parametrize("security", [128, 256])
+def test_shake_xof(kb, o2, security):
+    import torch
+    R = 168 if security == 128 else 136
+    b = wl.explicit(list(range(0, 2 * R + 3)) + [5000, 0, 1], seed=60 + security, gap=1, lead=3)
+    data, offs, lens, _ = _to_dev(b)
+    for out_len in (1, 3, 32, R - 1, R, R + 1, 3 * R + 5):
+        _say("shake", security, "out_len", out_len)
+        got = kb.keccak_batch_xof(security, data, offs, lens, out_len)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        for i in range(b.n):
+            m = b.data[b.offsets[i]:b.offsets[i] + b.lengths[i]].tobytes()
+            assert got[i].tobytes() == o2.shake(security, m, out_len), (out_len, i)
