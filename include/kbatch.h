@@ -54,8 +54,12 @@ enum kb_mode {
   KB_MODE_PERSISTENT = 0, /* bucket by block count, longest first, one persistent launch */
   KB_MODE_PLAIN = 1,      /* one thread per message in arrival order, one launch (the
                              paper's "one thread per message", Section 4.1) */
-  KB_MODE_PER_BUCKET = 2  /* bucket by block count, one plain launch per bucket (waits on
+  KB_MODE_PER_BUCKET = 2, /* bucket by block count, one plain launch per bucket (waits on
                              the host for the bucket sizes) */
+  KB_MODE_SPLIT = 3       /* latency form: five lanes of a wave share one state, eight
+                             messages per wave in arrival order (SHA3 variants only; the
+                             serial absorb chain of Section 3.2 runs about twice as fast
+                             per message, at a fraction of the batch throughput) */
 };
 
 /* Tuning knobs of the persistent form; a zero field means "library default". */
@@ -146,8 +150,11 @@ int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_dat
  * bound at capture time: replaying hashes whatever the bound buffers hold
  * then.  Each graph owns a private workspace (allocated at create, freed at
  * destroy), so direct calls and other graphs never disturb it; replays of
- * one graph must not overlap each other (replay it on one stream).  Only
- * the persistent and plain modes can be captured.
+ * one graph must not overlap each other (replay it on one stream).  The
+ * persistent, plain and split modes can be captured (not per-bucket, which
+ * waits on the host).  `stream` is where the workspace is prepared and the
+ * work recorded; a NULL stream records on a private stream, since the null
+ * stream cannot be captured.  A graph replays on any stream.
  */
 typedef struct kb_graph kb_graph;
 int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d_data,

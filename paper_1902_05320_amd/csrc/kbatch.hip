@@ -41,6 +41,7 @@
 
 #include "kbatch.h"
 #include "sponge_device.h"
+#include "split_device.h"
 
 using kb::kMixed;
 using kb::kShake128;
@@ -50,6 +51,9 @@ using kb::SpongeShape;
 
 namespace {
 
+#ifndef KB_OCC
+#define KB_OCC
+#endif
 constexpr int kBlock = 256;         // threads per workgroup of the hashing kernels
 constexpr uint32_t kKeyBins = 4096;  // block-count buckets
 constexpr int kPlanThreads = 1024;
@@ -101,21 +105,17 @@ __device__ __forceinline__ uint32_t key_of(uint64_t nb) {
   return nb >= kKeyBins - 1 ? kKeyBins - 1 : static_cast<uint32_t>(nb);
 }
 
-// Hash message i into its output slot of `stride` bytes (the digest size,
-// 64 in the mixed form, the output length for the XOFs).
+// Hash message i (`len` bytes at data + off, variant `var` in the mixed
+// form) into its output slot of `stride` bytes (the digest size, 64 in the
+// mixed form, the output length for the XOFs).
 template <int V>
-__device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
-                                             const uint64_t* __restrict__ offs,
-                                             const uint64_t* __restrict__ lens,
-                                             const uint8_t* __restrict__ vars, uint64_t i,
-                                             uint8_t* __restrict__ out, uint64_t stride,
-                                             uint32_t* row) {
-  int var = V;
-  if constexpr (V == kMixed) var = vars[i];
+__device__ __forceinline__ void hash_one(const uint8_t* __restrict__ data, uint64_t off,
+                                         uint64_t len, int var, uint64_t i,
+                                         uint8_t* __restrict__ out, uint64_t stride, uint32_t* row) {
   uint8_t* o = out + i * stride;
   if constexpr (V >= kShake128) {
     Lane A[25];
-    kb::sponge_hash<V>(A, data + offs[i], lens[i], var, row);
+    kb::sponge_hash<V>(A, data + off, len, var, row);
     kb::squeeze_xof<V>(A, o, stride);
     return;
   }
@@ -126,8 +126,18 @@ __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
     return;
   }
   Lane A[25];
-  kb::sponge_hash<V>(A, data + offs[i], lens[i], var, row);
+  kb::sponge_hash<V>(A, data + off, len, var, row);
   kb::store_digest<V>(o, A, var);
+}
+
+template <int V>
+__device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
+                                             const uint64_t* __restrict__ offs,
+                                             const uint64_t* __restrict__ lens,
+                                             const uint8_t* __restrict__ vars, uint64_t i,
+                                             uint8_t* __restrict__ out, uint64_t stride,
+                                             uint32_t* row) {
+  hash_one<V>(data, offs[i], lens[i], V == kMixed ? vars[i] : V, i, out, stride, row);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,7 +147,7 @@ __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
 // One thread per message (Section 4.1).  With `order`, thread p hashes
 // message order[first + p]; otherwise message first + p.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_plain(const uint8_t* __restrict__ data,
+__global__ __launch_bounds__(kBlock) KB_OCC void k_plain(const uint8_t* __restrict__ data,
                                                   const uint64_t* __restrict__ offs,
                                                   const uint64_t* __restrict__ lens,
                                                   const uint8_t* __restrict__ vars,
@@ -150,6 +160,62 @@ __global__ __launch_bounds__(kBlock) void k_plain(const uint8_t* __restrict__ da
   if (p >= count) return;
   const uint64_t i = order ? order[first + p] : first + p;
   hash_message<V>(data, offs, lens, vars, i, out, stride, lds + threadIdx.x * S::kRowDw);
+}
+
+// Lane-split form: each group of eight lanes hashes one message at a time,
+// message order[first + p] (or first + p) for p = group, group + groups, ...
+// One wave per workgroup, so a handful of messages spreads over SIMDs.
+constexpr int kSplitBlock = 64;
+constexpr int kSplitGroups = kSplitBlock / kb::split::kGroupLanes;
+
+template <int V>
+__global__ __launch_bounds__(kSplitBlock) void k_split(const uint8_t* __restrict__ data,
+                                                       const uint64_t* __restrict__ offs,
+                                                       const uint64_t* __restrict__ lens,
+                                                       const uint8_t* __restrict__ vars,
+                                                       const uint32_t* __restrict__ order,
+                                                       uint64_t first, uint64_t count,
+                                                       uint8_t* __restrict__ out, uint64_t stride) {
+  namespace sp = kb::split;
+  using S = SpongeShape<V>;
+  __shared__ uint64_t lds[kSplitGroups * sp::kGroupSlots + 1];
+  const uint32_t g = threadIdx.x / sp::kGroupLanes, t = threadIdx.x % sp::kGroupLanes;
+  uint64_t* zero = lds + kSplitGroups * sp::kGroupSlots;
+  if (threadIdx.x == 0) *zero = 0;
+  __syncthreads();
+  sp::SplitLane L;
+  sp::setup(L, t, lds + g * sp::kGroupSlots, zero);
+  const uint64_t groups = static_cast<uint64_t>(gridDim.x) * kSplitGroups;
+  const int slot_dw = V == kMixed ? 16 : kb::digest_bytes_of(V) / 4;
+  for (uint64_t p = static_cast<uint64_t>(blockIdx.x) * kSplitGroups + g; p < count; p += groups) {
+    const uint64_t i = order ? order[first + p] : first + p;
+    const int var = V == kMixed ? vars[i] : V;
+    uint32_t* o = reinterpret_cast<uint32_t*>(out + i * stride);
+    Lane a[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) a[j] = Lane{0u, 0u};
+    if (V == kMixed && var > 3) {  // no such variant: the slot is zeroed
+      sp::store_words(o, a, 0, slot_dw, L);
+      continue;
+    }
+    const uint64_t len = lens[i];
+    const uint8_t* msg = data + offs[i];
+    const int R = rate_of<V>(var);
+    const uint32_t sh = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(msg) & 3u);
+    const uint64_t nb = len / static_cast<uint64_t>(R) + 1u;
+    sp::BlockWords bw;
+    sp::load_words(bw, msg, sh, len, 0, R, L);
+    for (uint64_t b = 0; b < nb; ++b) {
+      const uint64_t boff = b * static_cast<uint64_t>(R);
+      const bool fin = b + 1 == nb;
+      sp::absorb_words(a, bw, sh, R, fin, fin ? static_cast<uint32_t>(len - boff) : 0u,
+                       S::kPadByte, L);
+      if (!fin) sp::load_words(bw, msg, sh, len, boff + R, R, L);
+      sp::split_permute(a, L);
+    }
+    const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
+    sp::store_words(o, a, dw, slot_dw, L);
+  }
 }
 
 // Persistent form: waves pop queue items until the queue is drained.  Every
@@ -179,7 +245,7 @@ __device__ __forceinline__ uint32_t simd_slot() {
 // empty, so the grid always drains.  In arrival order (uniform work) every
 // wave takes from the front at normal priority.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_persistent(
+__global__ __launch_bounds__(kBlock) KB_OCC void k_persistent(
     const uint8_t* __restrict__ data, const uint64_t* __restrict__ offs,
     const uint64_t* __restrict__ lens, const uint8_t* __restrict__ vars,
     const uint32_t* __restrict__ order, const WorkItem* __restrict__ items,
@@ -233,9 +299,32 @@ __global__ __launch_bounds__(kBlock) void k_persistent(
       __builtin_amdgcn_s_setprio(3);
     else
       __builtin_amdgcn_s_setprio(0);
-    for (uint32_t pos = it.begin + lane; pos < it.end; pos += 64u) {
-      const uint64_t i = ord ? ord[pos] : pos;
-      hash_message<V>(data, offs, lens, vars, i, out, stride, row);
+    // the next message's index and metadata are loaded while this one hashes
+    uint32_t pos = it.begin + lane;
+    uint64_t i = 0, off = 0, len = 0;
+    int var = V;
+    if (pos < it.end) {
+      i = ord ? ord[pos] : pos;
+      off = offs[i];
+      len = lens[i];
+      if constexpr (V == kMixed) var = vars[i];
+    }
+    while (pos < it.end) {
+      const uint32_t pn = pos + 64u;
+      uint64_t in = 0, offn = 0, lenn = 0;
+      int varn = V;
+      if (pn < it.end) {
+        in = ord ? ord[pn] : pn;
+        offn = offs[in];
+        lenn = lens[in];
+        if constexpr (V == kMixed) varn = vars[in];
+      }
+      hash_one<V>(data, off, len, var, i, out, stride, row);
+      pos = pn;
+      i = in;
+      off = offn;
+      len = lenn;
+      var = varn;
     }
   }
   __builtin_amdgcn_s_setprio(0);
@@ -255,7 +344,7 @@ struct TreeLevels {
 // level is separated by a workgroup barrier, which also orders the global
 // node writes of one level before the reads of the next.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_tree(const uint8_t* __restrict__ data, uint64_t total,
+__global__ __launch_bounds__(kBlock) KB_OCC void k_tree(const uint8_t* __restrict__ data, uint64_t total,
                                                  uint64_t leaf_size, uint8_t* __restrict__ nodes,
                                                  int first, int levels, TreeLevels lv) {
   using S = SpongeShape<V>;
@@ -722,6 +811,30 @@ int launch_plain(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
 }
 
 template <int V>
+int launch_split(const Batch& b, const uint32_t* order, uint64_t first, uint64_t count,
+                 hipStream_t s) {
+  if constexpr (V >= kShake128) {
+    return fail(KB_EINVAL, "the lane-split form hashes the SHA3 variants only");
+  } else {
+    if (!count) return KB_OK;
+    int dev = 0, cus = 0;
+    KB_HIP(hipGetDevice(&dev));
+    int rc = cu_count(dev, &cus);
+    if (rc) return rc;
+    // one group per message up to 16 waves per CU; beyond that groups loop
+    uint64_t grid = (count + kSplitGroups - 1) / kSplitGroups;
+    if (grid > static_cast<uint64_t>(16 * cus)) grid = 16 * cus;
+    {
+      TimedLaunch tl(s);
+      hipLaunchKernelGGL(k_split<V>, dim3(static_cast<uint32_t>(grid)), dim3(kSplitBlock), 0, s,
+                         b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
+    }
+    KB_HIP(hipGetLastError());
+    return KB_OK;
+  }
+}
+
+template <int V>
 int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, hipStream_t s) {
   uint32_t* hist = w.meta;
   uint32_t* start = w.meta + kKeyBins;
@@ -758,6 +871,7 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, h
 template <int V>
 int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Workspace* own) {
   if (mode == KB_MODE_PLAIN) return launch_plain<V>(b, nullptr, 0, b.n, s);
+  if (mode == KB_MODE_SPLIT) return launch_split<V>(b, nullptr, 0, b.n, s);
   if (b.n >= 0xFFFFFFFFull) return launch_plain<V>(b, nullptr, 0, b.n, s);  // 32-bit order[]
   Workspace* w = own;
   int rc = own ? KB_OK : get_ws(s, b.n, 0, &w);
@@ -822,7 +936,7 @@ int check_batch(const Batch& b, int mode) {
   if (b.variant != kMixed && b.variant != kShake128 && b.variant != kShake256 &&
       (b.variant < 0 || b.variant > 3))
     return fail(KB_EINVAL, "variant %d is not a SHA-3 variant (0..3)", b.variant);
-  if (mode < KB_MODE_PERSISTENT || mode > KB_MODE_PER_BUCKET)
+  if (mode < KB_MODE_PERSISTENT || mode > KB_MODE_SPLIT)
     return fail(KB_EINVAL, "unknown scheduling mode %d", mode);
   if (b.n == 0) return KB_OK;
   if (!b.data || !b.offs || !b.lens || !b.out || (b.variant == kMixed && !b.vars))
@@ -919,15 +1033,29 @@ int size_ws(Workspace& w, uint64_t msgs, uint64_t tree_bytes, hipStream_t s) {
 // Capture whatever `enqueue` puts on `stream` into a graph that owns `g`.
 template <class F>
 int capture(hipStream_t stream, F&& enqueue, kb_graph* g, kb_graph** out) {
+  // The null stream cannot be captured; record on a private stream then (a
+  // graph remembers its nodes, not the stream it was recorded on).
+  hipStream_t own = nullptr;
+  if (!stream) {
+    const hipError_t ec = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+    if (ec != hipSuccess) {
+      free_ws(g->ws);
+      delete g;
+      return fail(KB_EHIP, "hipStreamCreateWithFlags: %s", hipGetErrorString(ec));
+    }
+    stream = own;
+  }
   const hipError_t eb = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
   if (eb != hipSuccess) {
+    if (own) (void)hipStreamDestroy(own);
     free_ws(g->ws);
     delete g;
     return fail(KB_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(eb));
   }
-  int rc = enqueue();
+  int rc = enqueue(stream);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(stream, &graph);
+  if (own) (void)hipStreamDestroy(own);
   hipGraphExec_t exec = nullptr;
   if (rc == KB_OK && e != hipSuccess) rc = fail(KB_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
   if (rc == KB_OK) {
@@ -1116,8 +1244,8 @@ int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d
   if (!out) return fail(KB_EINVAL, "NULL output pointer");
   if (variant != -1 && (variant < 0 || variant > 3))
     return fail(KB_EINVAL, "variant %d is neither -1 (mixed) nor a SHA-3 variant", variant);
-  if (mode != KB_MODE_PERSISTENT && mode != KB_MODE_PLAIN)
-    return fail(KB_EINVAL, "only the persistent and plain modes can be captured");
+  if (mode == KB_MODE_PER_BUCKET)
+    return fail(KB_EINVAL, "the per-bucket mode waits on the host and cannot be captured");
   const int v = variant == -1 ? kMixed : variant;
   Batch b{v, d_variants, d_data, d_offsets, d_lengths, n, d_digests, out_stride(v)};
   int rc = check_batch(b, mode);
@@ -1134,7 +1262,8 @@ int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d
       return rc;
     }
   }
-  return capture(stream, [&]() { return n ? dispatch(b, mode, tile, stream, &g->ws) : KB_OK; }, g, out);
+  return capture(stream, [&](hipStream_t cs) { return n ? dispatch(b, mode, tile, cs, &g->ws) : KB_OK; },
+                 g, out);
 }
 
 int keccak_graph_create_merkle(int variant, const uint8_t* d_data, uint64_t total_len,
@@ -1153,12 +1282,12 @@ int keccak_graph_create_merkle(int variant, const uint8_t* d_data, uint64_t tota
     delete g;
     return rc;
   }
-  return capture(stream, [&]() {
+  return capture(stream, [&](hipStream_t cs) {
         switch (variant) {
-          case 0: return merkle_impl<0>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
-          case 1: return merkle_impl<1>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
-          case 2: return merkle_impl<2>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
-          default: return merkle_impl<3>(d_data, total_len, leaf_size, d_root, stream, &g->ws);
+          case 0: return merkle_impl<0>(d_data, total_len, leaf_size, d_root, cs, &g->ws);
+          case 1: return merkle_impl<1>(d_data, total_len, leaf_size, d_root, cs, &g->ws);
+          case 2: return merkle_impl<2>(d_data, total_len, leaf_size, d_root, cs, &g->ws);
+          default: return merkle_impl<3>(d_data, total_len, leaf_size, d_root, cs, &g->ws);
         }
       }, g, out);
 }

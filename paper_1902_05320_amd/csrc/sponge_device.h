@@ -3,8 +3,9 @@
 // Each block of the padded message P = M || 01 || pad10*1 is staged through a
 // per-thread row of LDS before it is xored into the state:
 //   1. the 16-byte-aligned chunks that hold the block's bytes are read with
-//      global_load_dwordx4 and stored to the row unchanged, so a block at any
-//      byte offset costs at most ceil((R + 15) / 16) vector loads;
+//      global_load_dwordx4 (for the next block while the current one is
+//      permuted) and stored to the row unchanged, so a block at any byte
+//      offset costs at most ceil((R + 15) / 16) vector loads;
 //   2. on the final block the bytes past the message end are cleared and the
 //      suffix/padding bytes are written with byte-granular LDS stores: 0x06
 //      (bits 0,1 of the suffix "01" then the first pad bit; 0x1F for the
@@ -36,8 +37,10 @@ struct SpongeShape {
   static constexpr int kMaxRateDw = kMaxRate / 4;
   // 16-byte chunks that can hold R bytes starting at any offset mod 16
   static constexpr int kChunks = (kMaxRate + 15 + 15) / 16;
-  // chunk area plus room for the padding stores past the last chunk
-  static constexpr int kRowDw = kChunks * 4 + 4;
+  // the LDS row is the chunk area; the read-back (dwords s16/4 .. s16/4 + R/4,
+  // s16 < 16) stays inside it, and clearing stores past it are dropped
+  static constexpr int kRowDw = kChunks * 4;
+  static_assert(3 + kMaxRate / 4 < kRowDw, "read-back must stay inside the row");
   static constexpr int kMaxDigestDw = V == kMixed ? 16 : V >= kShake128 ? 0 : digest_bytes_of(V) / 4;
   // the suffix bits and the first pad bit, as the byte after the message:
   // SHA-3 "01" then 1 -> 0x06; SHAKE "1111" then 1 -> 0x1F
@@ -47,42 +50,55 @@ struct SpongeShape {
 __device__ __forceinline__ int rate_bytes_rt(int v) { return 200 - 2 * (v == 0 ? 28 : v == 1 ? 32 : v == 2 ? 48 : 64); }
 __device__ __forceinline__ int digest_bytes_rt(int v) { return v == 0 ? 28 : v == 1 ? 32 : v == 2 ? 48 : 64; }
 
-// Stage one rate block of the padded message into `row` and return it as
-// little-endian dwords in w[0 .. kMaxRateDw).  `p` points at the block's
-// first message byte, `rem` is min(bytes left, R), `fin` marks the final
-// block (rem < R then).
+// The 16-byte-aligned chunks holding one block's bytes: `p` points at the
+// block's first message byte, `rem` = min(bytes left, R).  Only chunks
+// holding at least one message byte are read; the rest are zero.
 template <int V>
-__device__ __forceinline__ void stage_block(uint32_t* __restrict__ row, const uint8_t* p,
+struct BlockChunks {
+  uint4 c[SpongeShape<V>::kChunks];
+  uint32_t s16;  // p mod 16
+};
+
+template <int V>
+__device__ __forceinline__ void load_block(BlockChunks<V>& bc, const uint8_t* p, uint32_t rem) {
+  using S = SpongeShape<V>;
+  bc.s16 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p) & 15u);
+  // derive the aligned base by pointer arithmetic (not from an integer) so
+  // the loads stay in the global address space
+  const uint4* base = reinterpret_cast<const uint4*>(p - bc.s16);
+  const uint32_t nv = bc.s16 + rem;
+#pragma unroll
+  for (int j = 0; j < S::kChunks; ++j) {
+    bc.c[j] = make_uint4(0u, 0u, 0u, 0u);
+    if (rem != 0u && 16u * j < nv) bc.c[j] = base[j];
+  }
+}
+
+// Stage loaded chunks through `row`, apply the padding on the final block
+// (`fin`, rem < R then) and return the block as little-endian dwords
+// w[0 .. kMaxRateDw).
+template <int V>
+__device__ __forceinline__ void stage_block(uint32_t* __restrict__ row, const BlockChunks<V>& bc,
                                             uint32_t rem, int R, bool fin,
                                             uint32_t (&w)[SpongeShape<V>::kMaxRateDw]) {
   using S = SpongeShape<V>;
-  const uint32_t s16 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p) & 15u);
-  // derive the aligned base by pointer arithmetic (not from an integer) so
-  // the loads stay in the global address space
-  const uint4* base = reinterpret_cast<const uint4*>(p - s16);
+  const uint32_t s16 = bc.s16;
   const uint32_t nv = s16 + rem;  // row bytes [s16, nv) hold message bytes
-  // issue every chunk load before the first LDS store
-  uint4 c[S::kChunks];
-#pragma unroll
-  for (int j = 0; j < S::kChunks; ++j) {
-    c[j] = make_uint4(0u, 0u, 0u, 0u);
-    // only chunks holding at least one message byte are read
-    if (rem != 0u && 16u * j < nv) c[j] = base[j];
-  }
   uint4* row4 = reinterpret_cast<uint4*>(row);
 #pragma unroll
-  for (int j = 0; j < S::kChunks; ++j) row4[j] = c[j];
+  for (int j = 0; j < S::kChunks; ++j) row4[j] = bc.c[j];
   if (fin) {
     // clear the tail of the last chunk: up to three whole dwords past the
     // dword holding byte nv, then bytes nv..nv+2 (suffix byte first)
+    // (nv < s16 + R <= 4 kRowDw, so the suffix byte is always inside the row)
     const uint32_t d0 = (nv + 3u) >> 2;
-    row[d0] = 0u;
-    row[d0 + 1] = 0u;
-    row[d0 + 2] = 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < 3; ++k)
+      if (d0 + k < static_cast<uint32_t>(S::kRowDw)) row[d0 + k] = 0u;
     uint8_t* rb = reinterpret_cast<uint8_t*>(row);
     rb[nv] = S::kPadByte;
-    rb[nv + 1] = 0u;
-    rb[nv + 2] = 0u;
+    if (nv + 1u < 4u * S::kRowDw) rb[nv + 1] = 0u;
+    if (nv + 2u < 4u * S::kRowDw) rb[nv + 2] = 0u;
     rb[s16 + R - 1] = rem + 1u == static_cast<uint32_t>(R) ? (S::kPadByte | 0x80u) : 0x80u;
   }
   const uint32_t* src = row + (s16 >> 2);
@@ -94,6 +110,17 @@ __device__ __forceinline__ void stage_block(uint32_t* __restrict__ row, const ui
 // Absorb the whole message and run the permutation on every block; on return
 // A holds Keccak-f[1600] of the last absorbed state, i.e. the squeezed output
 // lanes (d <= r for every SHA-3 variant, so one squeeze suffices).
+// With prefetch on, the chunks of block b+1 are loaded into registers before
+// the permutation of block b and land while it runs, so a multi-block
+// message's chain of permutations does not wait for HBM between blocks.  It
+// costs the registers of one block of chunks; the mixed-variant form leaves
+// it off.
+#ifndef KB_PREFETCH_ON
+#define KB_PREFETCH_ON 1
+#endif
+template <int V>
+constexpr bool kPrefetch = KB_PREFETCH_ON && V != kMixed;
+
 template <int V>
 __device__ __forceinline__ void sponge_hash(Lane (&A)[25], const uint8_t* msg, uint64_t len,
                                             int var, uint32_t* __restrict__ row) {
@@ -103,13 +130,20 @@ __device__ __forceinline__ void sponge_hash(Lane (&A)[25], const uint8_t* msg, u
   // blocks of the padded message: the 2 suffix bits and the pad fit after
   // any byte-aligned message, so nb = floor(L / R) + 1
   const uint64_t nb = len / static_cast<uint64_t>(R) + 1u;
+  BlockChunks<V> bc;
+  if (kPrefetch<V>) load_block<V>(bc, msg, nb == 1 ? static_cast<uint32_t>(len) : static_cast<uint32_t>(R));
   for (uint64_t b = 0; b < nb; ++b) {
     const bool fin = b + 1u == nb;
-    const uint8_t* p = msg + b * static_cast<uint64_t>(R);
-    const uint32_t rem = fin ? static_cast<uint32_t>(len - b * static_cast<uint64_t>(R))
-                             : static_cast<uint32_t>(R);
+    const uint64_t off = b * static_cast<uint64_t>(R);
+    const uint32_t rem = fin ? static_cast<uint32_t>(len - off) : static_cast<uint32_t>(R);
+    if (!kPrefetch<V>) load_block<V>(bc, msg + off, rem);
     uint32_t w[S::kMaxRateDw];
-    stage_block<V>(row, p, rem, R, fin, w);
+    stage_block<V>(row, bc, rem, R, fin, w);
+    if (kPrefetch<V> && !fin) {
+      const uint64_t off1 = off + static_cast<uint64_t>(R);
+      load_block<V>(bc, msg + off1,
+                    b + 2u == nb ? static_cast<uint32_t>(len - off1) : static_cast<uint32_t>(R));
+    }
     if (b == 0) {
 #pragma unroll
       for (int k = 0; k < 50; ++k) {

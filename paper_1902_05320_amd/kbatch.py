@@ -21,8 +21,8 @@ VARIANTS = {"sha3_224": 0, "sha3_256": 1, "sha3_384": 2, "sha3_512": 3}
 DIGEST_BYTES = (28, 32, 48, 64)
 RATE_BYTES = (144, 136, 104, 72)
 
-MODE_PERSISTENT, MODE_PLAIN, MODE_PER_BUCKET = 0, 1, 2
-MODES = {"persistent": 0, "plain": 1, "per_bucket": 2}
+MODE_PERSISTENT, MODE_PLAIN, MODE_PER_BUCKET, MODE_SPLIT = 0, 1, 2, 3
+MODES = {"persistent": 0, "plain": 1, "per_bucket": 2, "split": 3}
 
 KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
 
@@ -187,7 +187,7 @@ def keccak_batch(variant, data: torch.Tensor, offsets: torch.Tensor, lengths: to
                  out: torch.Tensor | None = None, stream=None, mode="persistent",
                  tile: Tile | None = None, check_bounds: bool = True) -> torch.Tensor:
     """SHA-3 digests of every (offset, length) slice of `data`; returns
-    uint8[n, D] on the device.  `mode` is persistent, plain or per_bucket."""
+    uint8[n, D] on the device.  `mode` is persistent, plain, per_bucket or split."""
     _require_gpu()
     lib = load_library()
     v = variant_id(variant)

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 RATES = (144, 136, 104, 72)
 DIGEST = (28, 32, 48, 64)
-MODES = ("persistent", "plain", "per_bucket")
+MODES = ("persistent", "plain", "per_bucket", "split")
 
 
 @pytest.fixture(scope="module")
@@ -99,31 +99,33 @@ def test_uneven_single_variant(kb, o2, v):
     assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
 
 
-def test_mixed_invalid_variant_slot_is_zero(kb, o2):
+@pytest.mark.parametrize("mode", ["persistent", "split"])
+def test_mixed_invalid_variant_slot_is_zero(kb, o2, mode):
     b = wl.explicit([10, 200, 0, 77], seed=5, variant=np.array([1, 9, 3, 255], dtype=np.uint8))
-    _say("mixed invalid variant")
-    got = _gpu_mixed(kb, b)
+    _say("mixed invalid variant", mode)
+    got = _gpu_mixed(kb, b, mode)
     assert not got[1].any() and not got[3].any()
     want = o2.sha3_batch_mixed(np.array([1, 1, 3, 3], np.uint8), b.data, b.offsets, b.lengths)
     assert (got[0] == want[0]).all() and (got[2] == want[2]).all()
 
 
-def test_edge_cases(kb, o2):
+@pytest.mark.parametrize("mode", ["persistent", "split"])
+def test_edge_cases(kb, o2, mode):
     import torch
-    _say("edge: empty batch")
+    _say("edge: empty batch", mode)
     data = torch.zeros(16, dtype=torch.uint8, device="cuda")
     empty = torch.zeros(0, dtype=torch.int64, device="cuda")
-    out = kb.keccak_batch(1, data, empty, empty)
+    out = kb.keccak_batch(1, data, empty, empty, mode=mode)
     assert out.shape == (0, 32)
     _say("edge: all-empty messages")
     b = wl.explicit([0] * 300, seed=6)
-    got = _gpu_batch(kb, 1, b)
+    got = _gpu_batch(kb, 1, b, mode)
     want = o2.sha3_batch(256, b.data, b.offsets, b.lengths)
     assert (got == want).all()
     _say("edge: one long message")
     b = wl.explicit([1_000_003], seed=7, lead=9)
     for v in range(4):
-        got = _gpu_batch(kb, v, b)
+        got = _gpu_batch(kb, v, b, mode)
         want = o2.sha3_batch(8 * DIGEST[v], b.data, b.offsets, b.lengths)
         assert (got == want).all(), v
     _say("edge: overlapping slices ending at the buffer end")
@@ -134,7 +136,7 @@ def test_edge_cases(kb, o2):
     offs = buf.size - lens - rng.integers(0, 3, n)  # most slices end within 2 bytes of the end
     offs = np.maximum(offs, 0)
     bt = wl.Batch(buf, offs.astype(np.int64), lens.astype(np.int64), np.ones(n, np.uint8), 8, "ov")
-    got = _gpu_batch(kb, 1, bt)
+    got = _gpu_batch(kb, 1, bt, mode)
     want = o2.sha3_batch(256, bt.data, bt.offsets, bt.lengths)
     assert (got == want).all()
 

@@ -76,7 +76,7 @@ def test_autotune_candidates_pass_parity(kb, o2):
     assert np.array_equal(got, o2.sha3_batch(256, b.data, b.offsets, b.lengths))
 
 
-@pytest.mark.parametrize("mode", ["persistent", "plain"])
+@pytest.mark.parametrize("mode", ["persistent", "plain", "split"])
 def test_graph_replays_equal_eager(kb, mode):
     import torch
     b = wl.uneven(20000, 5000, seed=53)
