@@ -88,10 +88,14 @@ def cpu_baseline(batch, target_s: float = 10.0) -> dict:
                       f"lane-level C oracle on {threads} host threads, {dt:.1f} s"}
 
 
-def time_steps(torch, fn, steps, warmup):
+def time_steps(torch, fn, steps, warmup, on_timed=None):
+    """Mean wall time of `steps` calls after `warmup` untimed ones; `on_timed`
+    runs between the two (to arm the kernel timing hooks for the timed steps)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if on_timed:
+        on_timed()
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
@@ -115,11 +119,10 @@ def bench_uneven(args, kbatch, workloads, torch, dev):
     for mode in ("persistent", "plain", "per_bucket"):
         fn = lambda: kbatch.keccak_batch_mixed(var, data, offs, lens, out=out, mode=mode,
                                                check_bounds=False)
-        kbatch.timing_enable(True)
-        t = time_steps(torch, fn, args.steps, args.warmup)
+        t = time_steps(torch, fn, args.steps, args.warmup, lambda: kbatch.timing_enable(True))
         k_ms, k_n = kbatch.timing_read()
         kbatch.timing_enable(False)
-        steps_timed = args.steps + args.warmup
+        steps_timed = args.steps
         res[mode] = {"ms_per_step": round(t * 1e3, 4), "mhash_s": round(b.n / t / 1e6, 2),
                      "gb_per_s_hashed": round(b.total_bytes / t / 1e9, 2),
                      "kernel_ms_per_step": round(k_ms / steps_timed, 4),
@@ -141,12 +144,11 @@ def bench_merkle(args, kbatch, workloads, torch, dev):
     leaves = total // 4096
     perms = leaves * (4096 // 136 + 1) + (leaves - 1)
     kbatch.reserve(0, leaves)
-    kbatch.timing_enable(True)
     t = time_steps(torch, lambda: kbatch.merkle_root(1, data, 4096, out=root), args.steps,
-                   args.warmup)
+                   args.warmup, lambda: kbatch.timing_enable(True))
     k_ms, k_n = kbatch.timing_read()
     kbatch.timing_enable(False)
-    steps_timed = args.steps + args.warmup
+    steps_timed = args.steps
     print(json.dumps({"config": {"workload": "merkle_1GiB_4KiB_leaves_sha3_256", "seed": 5,
                                  "leaves": leaves, "permutations": perms},
                       "ms_per_root": round(t * 1e3, 4), "gb_per_s_hashed": round(total / t / 1e9, 2),
@@ -154,6 +156,34 @@ def bench_merkle(args, kbatch, workloads, torch, dev):
                       "launches_per_root": k_n // steps_timed,
                       "alu_frac_whole_root": round(perms * OPS_PER_PERMUTATION / t / 1e12
                                                    / PEAK_INT32_TOPS, 4)}), flush=True)
+
+
+def bench_latency(args, kbatch, workloads, torch, dev):
+    """Few long messages: one thread per message (plain, persistent) against
+    five lanes per message (split).  Wall time per batch and per absorbed
+    block of the longest chain; digests must agree across the forms."""
+    cases = ((1, 1 << 20), (8, 1 << 16), (512, 1 << 16), (4096, 1 << 14), (32768, 1 << 12))
+    rows = []
+    for k, size in cases:
+        b = workloads.uniform(k, size, seed=6)
+        data = torch.from_numpy(b.data).to(dev)
+        offs = torch.from_numpy(b.offsets).to(dev)
+        lens = torch.from_numpy(b.lengths).to(dev)
+        nb = size // 136 + 1
+        row = {"messages": k, "bytes_each": size, "blocks_each": nb}
+        ref = None
+        for mode in ("plain", "persistent", "split"):
+            out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
+            fn = lambda: kbatch.keccak_batch(1, data, offs, lens, out=out, mode=mode,
+                                             check_bounds=False)
+            t = time_steps(torch, fn, args.steps, args.warmup)
+            row[mode] = {"ms": round(t * 1e3, 4), "us_per_block": round(t * 1e6 / nb, 3)}
+            ref = out.clone() if ref is None else ref
+            row[mode]["same_digests"] = bool(torch.equal(out, ref))
+        print(f"[bench] latency {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+    print(json.dumps({"config": {"workload": "latency_few_long_sha3_256", "seed": 6},
+                      "steps": args.steps, "warmup": args.warmup, "cases": rows}), flush=True)
 
 
 def bench_serving(args, kbatch, workloads, torch, dev):
@@ -235,10 +265,11 @@ def main():
                     help="only run the library's copy probe over MIB MiB (for counter scaling)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="uniform",
-                    choices=("uniform", "uneven", "merkle", "serving"),
+                    choices=("uniform", "uneven", "merkle", "serving", "latency"),
                     help="uniform: 2^24 x 64 B SHA3-256 (the reported metric); uneven: 2^20 "
                          "mixed-variant messages, log-uniform lengths in [0, 16 KiB]; merkle: "
-                         "1 GiB in 4 KiB leaves")
+                         "1 GiB in 4 KiB leaves; serving: Poisson request stream; latency: "
+                         "1 to 32768 long messages, one thread vs five lanes per message")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -269,6 +300,8 @@ def main():
         return bench_merkle(args, kbatch, workloads, torch, dev)
     if args.workload == "serving":
         return bench_serving(args, kbatch, workloads, torch, dev)
+    if args.workload == "latency":
+        return bench_latency(args, kbatch, workloads, torch, dev)
 
     print(f"[bench] generating {N_MSGS} x {MSG_BYTES} B (seed {SEED})", file=sys.stderr, flush=True)
     batch = workloads.uniform(N_MSGS, MSG_BYTES, seed=SEED, variant=VARIANT)

@@ -8,8 +8,8 @@
 //               wave of arrival order, the lane-slots a wave would idle
 //   k_plan      one workgroup: keep arrival order if it idles <= 2 % of the
 //               lane slots, else bucket starts in descending nb (longest
-//               first); queue-item counts per bucket (about `steps_per_item`
-//               permutations per lane each)
+//               first) and queue-item counts per bucket (about
+//               `steps_per_item` permutations per lane each)
 //   k_items     one thread per queue item: its message range and bucket
 //   k_scatter   counting-sort scatter of message indices into `order`
 //               (skipped when arrival order is kept)
@@ -51,12 +51,9 @@ using kb::SpongeShape;
 
 namespace {
 
-#ifndef KB_OCC
-#define KB_OCC
-#endif
 constexpr int kBlock = 256;         // threads per workgroup of the hashing kernels
+constexpr int kTreeTop = 1024;      // threads of the workgroup that reduces a tree's last levels
 constexpr uint32_t kKeyBins = 4096;  // block-count buckets
-constexpr int kPlanThreads = 1024;
 constexpr int kScatterTile = 4096;  // messages per scatter workgroup
 
 // control words (uint32 indices into the ctl area)
@@ -147,7 +144,7 @@ __device__ __forceinline__ void hash_message(const uint8_t* __restrict__ data,
 // One thread per message (Section 4.1).  With `order`, thread p hashes
 // message order[first + p]; otherwise message first + p.
 template <int V>
-__global__ __launch_bounds__(kBlock) KB_OCC void k_plain(const uint8_t* __restrict__ data,
+__global__ __launch_bounds__(kBlock) void k_plain(const uint8_t* __restrict__ data,
                                                   const uint64_t* __restrict__ offs,
                                                   const uint64_t* __restrict__ lens,
                                                   const uint8_t* __restrict__ vars,
@@ -160,6 +157,38 @@ __global__ __launch_bounds__(kBlock) KB_OCC void k_plain(const uint8_t* __restri
   if (p >= count) return;
   const uint64_t i = order ? order[first + p] : first + p;
   hash_message<V>(data, offs, lens, vars, i, out, stride, lds + threadIdx.x * S::kRowDw);
+}
+
+// One message hashed by a group of eight lanes in the split form (`len`
+// bytes at msg, variant `var`); the digest's dwords go to o[0 .. slot_dw),
+// zero past the digest.  With PF the next block's words are loaded before
+// the current block's permutation (for long messages); without, each block
+// is loaded when it is absorbed (fewer registers, for one- and two-block
+// tree nodes).
+template <int V, bool PF = true>
+__device__ __forceinline__ void split_hash(const uint8_t* msg, uint64_t len, int var, uint32_t* o,
+                                           int slot_dw, const kb::split::SplitLane& L) {
+  namespace sp = kb::split;
+  using S = SpongeShape<V>;
+  Lane a[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) a[j] = Lane{0u, 0u};
+  const int R = rate_of<V>(var);
+  const uint32_t sh = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(msg) & 3u);
+  const uint64_t nb = len / static_cast<uint64_t>(R) + 1u;
+  sp::BlockWords bw;
+  if (PF) sp::load_words(bw, msg, sh, len, 0, R, L);
+  for (uint64_t b = 0; b < nb; ++b) {
+    const uint64_t boff = b * static_cast<uint64_t>(R);
+    const bool fin = b + 1 == nb;
+    if (!PF) sp::load_words(bw, msg, sh, len, boff, R, L);
+    sp::absorb_words(a, bw, sh, R, fin, fin ? static_cast<uint32_t>(len - boff) : 0u,
+                     S::kPadByte, L);
+    if (PF && !fin) sp::load_words(bw, msg, sh, len, boff + R, R, L);
+    sp::split_permute(a, L);
+  }
+  const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
+  sp::store_words(o, a, dw, slot_dw, L);
 }
 
 // Lane-split form: each group of eight lanes hashes one message at a time,
@@ -177,7 +206,6 @@ __global__ __launch_bounds__(kSplitBlock) void k_split(const uint8_t* __restrict
                                                        uint64_t first, uint64_t count,
                                                        uint8_t* __restrict__ out, uint64_t stride) {
   namespace sp = kb::split;
-  using S = SpongeShape<V>;
   __shared__ uint64_t lds[kSplitGroups * sp::kGroupSlots + 1];
   const uint32_t g = threadIdx.x / sp::kGroupLanes, t = threadIdx.x % sp::kGroupLanes;
   uint64_t* zero = lds + kSplitGroups * sp::kGroupSlots;
@@ -191,30 +219,14 @@ __global__ __launch_bounds__(kSplitBlock) void k_split(const uint8_t* __restrict
     const uint64_t i = order ? order[first + p] : first + p;
     const int var = V == kMixed ? vars[i] : V;
     uint32_t* o = reinterpret_cast<uint32_t*>(out + i * stride);
-    Lane a[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) a[j] = Lane{0u, 0u};
     if (V == kMixed && var > 3) {  // no such variant: the slot is zeroed
-      sp::store_words(o, a, 0, slot_dw, L);
+      Lane z[5];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) z[j] = Lane{0u, 0u};
+      sp::store_words(o, z, 0, slot_dw, L);
       continue;
     }
-    const uint64_t len = lens[i];
-    const uint8_t* msg = data + offs[i];
-    const int R = rate_of<V>(var);
-    const uint32_t sh = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(msg) & 3u);
-    const uint64_t nb = len / static_cast<uint64_t>(R) + 1u;
-    sp::BlockWords bw;
-    sp::load_words(bw, msg, sh, len, 0, R, L);
-    for (uint64_t b = 0; b < nb; ++b) {
-      const uint64_t boff = b * static_cast<uint64_t>(R);
-      const bool fin = b + 1 == nb;
-      sp::absorb_words(a, bw, sh, R, fin, fin ? static_cast<uint32_t>(len - boff) : 0u,
-                       S::kPadByte, L);
-      if (!fin) sp::load_words(bw, msg, sh, len, boff + R, R, L);
-      sp::split_permute(a, L);
-    }
-    const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
-    sp::store_words(o, a, dw, slot_dw, L);
+    split_hash<V>(data + offs[i], lens[i], var, o, slot_dw, L);
   }
 }
 
@@ -245,7 +257,7 @@ __device__ __forceinline__ uint32_t simd_slot() {
 // empty, so the grid always drains.  In arrival order (uniform work) every
 // wave takes from the front at normal priority.
 template <int V>
-__global__ __launch_bounds__(kBlock) KB_OCC void k_persistent(
+__global__ __launch_bounds__(kBlock) void k_persistent(
     const uint8_t* __restrict__ data, const uint64_t* __restrict__ offs,
     const uint64_t* __restrict__ lens, const uint8_t* __restrict__ vars,
     const uint32_t* __restrict__ order, const WorkItem* __restrict__ items,
@@ -338,47 +350,89 @@ struct TreeLevels {
   uint64_t off[64];
 };
 
-// Workgroup w owns nodes [256 w, 256 w + 256) of level `first` and reduces
-// them `levels` levels.  first == 0: it also hashes those leaves (leaf i is
+// Workgroup w owns nodes [T w, T w + T) of level `first` and reduces them
+// `levels` levels.  first == 0: it also hashes those leaves (leaf i is
 // min(leaf_size, total - i * leaf_size) bytes at data + i * leaf_size).  Each
 // level is separated by a workgroup barrier, which also orders the global
-// node writes of one level before the reads of the next.
-template <int V>
-__global__ __launch_bounds__(kBlock) KB_OCC void k_tree(const uint8_t* __restrict__ data, uint64_t total,
-                                                 uint64_t leaf_size, uint8_t* __restrict__ nodes,
-                                                 int first, int levels, TreeLevels lv) {
+// node writes of one level before the reads of the next.  The node of level
+// `top` (the root) is written to `root`.
+//
+// A level with more pairs per workgroup than the workgroup has 8-lane groups
+// hashes one pair per thread; the narrower levels at the top of each
+// workgroup's subtree, where one thread per pair would leave a wave's worth
+// of permutation latency for a handful of lanes, hash one pair per group in
+// the lane-split form (five lanes per state, about twice as fast per
+// permutation).  The split form's exchange area reuses the staging rows,
+// which no level uses after the first split one.
+template <int V, int T, bool PF>
+__global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, uint64_t total,
+                                            uint64_t leaf_size, uint8_t* __restrict__ nodes,
+                                            uint8_t* __restrict__ root, int first, int levels,
+                                            int top, TreeLevels lv) {
+  namespace sp = kb::split;
   using S = SpongeShape<V>;
   constexpr uint64_t D = kb::digest_bytes_of(V);
-  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
+  constexpr int kGroups = T / sp::kGroupLanes;
+  // SHA3-512's leaf kernel fits four waves per SIMD (125 VGPRs) only without
+  // the split path (148), and its leaves are the long chains, so there the
+  // in-workgroup levels stay one pair per thread.
+  constexpr bool kSplitLevels = !(V == 3 && T == kBlock);
+  __shared__ __align__(16) uint32_t lds[T * S::kRowDw];
+  static_assert(2 * (kGroups * sp::kGroupSlots + 1) <= T * S::kRowDw,
+                "the split exchange area fits in the staging rows");
   uint32_t* row = lds + threadIdx.x * S::kRowDw;
   const uint64_t w = blockIdx.x;
+  auto dst_of = [&](int level, uint64_t j) -> uint8_t* {
+    return level == top ? root : nodes + lv.off[level] + j * D;
+  };
   if (first == 0) {
-    const uint64_t i = w * kBlock + threadIdx.x;
+    const uint64_t i = w * T + threadIdx.x;
     if (i < lv.m[0]) {
       const uint64_t off = i * leaf_size;
       const uint64_t len = total - off < leaf_size ? total - off : leaf_size;
       Lane A[25];
-      kb::sponge_hash<V>(A, data + off, len, V, row);
-      kb::store_digest<V>(nodes + lv.off[0] + i * D, A, V);
+      kb::sponge_hash<V, PF>(A, data + off, len, V, row);
+      kb::store_digest<V>(dst_of(0, i), A, V);
     }
   }
   for (int k = 0; k < levels; ++k) {
     const int l = first + k;  // reading level l, writing level l + 1
     __syncthreads();
-    const uint64_t span = static_cast<uint64_t>(kBlock) >> (k + 1);
-    const uint64_t j = w * span + threadIdx.x;
-    if (threadIdx.x < span && j < lv.m[l + 1]) {
-      const uint8_t* src = nodes + lv.off[l] + 2 * j * D;
-      uint8_t* dst = nodes + lv.off[l + 1] + j * D;
-      if (2 * j + 1 < lv.m[l]) {
-        Lane A[25];
-        kb::sponge_hash<V>(A, src, 2 * D, V, row);
-        kb::store_digest<V>(dst, A, V);
-      } else {
-        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
-        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+    const uint64_t span = static_cast<uint64_t>(T) >> (k + 1);  // pairs of this workgroup
+    if (!kSplitLevels || span > static_cast<uint64_t>(kGroups)) {
+      const uint64_t j = w * span + threadIdx.x;
+      if (threadIdx.x < span && j < lv.m[l + 1]) {
+        const uint8_t* src = nodes + lv.off[l] + 2 * j * D;
+        uint8_t* dst = dst_of(l + 1, j);
+        if (2 * j + 1 < lv.m[l]) {
+          Lane A[25];
+          kb::sponge_hash<V, PF>(A, src, 2 * D, V, row);
+          kb::store_digest<V>(dst, A, V);
+        } else {
+          const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+          uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
 #pragma unroll
-        for (int q = 0; q < static_cast<int>(D / 4); ++q) d32[q] = s32[q];
+          for (int q = 0; q < static_cast<int>(D / 4); ++q) d32[q] = s32[q];
+        }
+      }
+    } else {
+      uint64_t* area = reinterpret_cast<uint64_t*>(lds);
+      uint64_t* zero = area + kGroups * sp::kGroupSlots;
+      if (threadIdx.x == 0) *zero = 0;
+      __syncthreads();
+      const uint32_t g = threadIdx.x / sp::kGroupLanes, t = threadIdx.x % sp::kGroupLanes;
+      const uint64_t j = w * span + g;
+      if (g < span && j < lv.m[l + 1]) {
+        const uint8_t* src = nodes + lv.off[l] + 2 * j * D;
+        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_of(l + 1, j));
+        if (2 * j + 1 < lv.m[l]) {
+          sp::SplitLane L;
+          sp::setup(L, t, area + g * sp::kGroupSlots, zero);
+          split_hash<V, false>(src, 2 * D, V, d32, static_cast<int>(D / 4), L);
+        } else {
+          const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+          for (uint32_t q = t; q < D / 4; q += sp::kGroupLanes) d32[q] = s32[q];
+        }
       }
     }
   }
@@ -412,12 +466,127 @@ __device__ __forceinline__ uint32_t key_at(const uint64_t* __restrict__ lens,
   return key_of(blocks_of<V>(lens[i], V == kMixed ? vars[i] : V));
 }
 
+// One 64-message chunk of arrival order (lane 0 always holds a message,
+// `cnt` of the 64 lanes do).  When every message of the chunk has the same
+// length and variant (the common case for uniform batches) the block count
+// is worked out once and one LDS atomic records the chunk; otherwise every
+// lane adds its own key and the chunk's idle lane-slots (cnt * max - sum)
+// are accumulated.  `useful` and `idle` stay wave-uniform.
+template <int V>
+__device__ __forceinline__ void count_chunk(uint64_t len, int var, bool valid, uint32_t cnt,
+                                            uint32_t lane, uint32_t* lhist, uint64_t& useful,
+                                            uint64_t& idle, uint32_t& kmax) {
+  const uint32_t lo0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(len));
+  const uint32_t hi0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(len >> 32));
+  const uint64_t len0 = (static_cast<uint64_t>(hi0) << 32) | lo0;
+  const int var0 = V == kMixed ? __builtin_amdgcn_readfirstlane(var) : V;
+  if (__ballot(valid && (len != len0 || var != var0)) == 0) {
+    const uint32_t key = key_of(blocks_of<V>(len0, var0));
+    if (lane == 0) atomicAdd(&lhist[key], cnt);
+    useful += static_cast<uint64_t>(key) * cnt;
+    kmax = key > kmax ? key : kmax;
+  } else {
+    const uint32_t key = valid ? key_of(blocks_of<V>(len, var)) : 0u;
+    kmax = key > kmax ? key : kmax;
+    if (valid) atomicAdd(&lhist[key], 1u);
+    const uint32_t sm = wave_sum(key), mx = wave_max(key);
+    useful += sm;
+    idle += static_cast<uint64_t>(mx) * cnt - sm;
+  }
+}
+
+// Inclusive prefix sum over the kBlock threads of a workgroup.
+__device__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* scratch) {
+  const uint32_t t = threadIdx.x;
+  scratch[t] = v;
+  __syncthreads();
+  for (uint32_t d = 1; d < kBlock; d <<= 1) {
+    const uint32_t add = t >= d ? scratch[t - d] : 0u;
+    __syncthreads();
+    scratch[t] += add;
+    __syncthreads();
+  }
+  const uint32_t r = scratch[t];
+  __syncthreads();
+  return r;
+}
+
+// Messages per queue item in a bucket of `key` blocks: 64 lanes times enough
+// messages that one item is about `steps` permutations per lane.
+__device__ __forceinline__ uint32_t item_msgs(uint32_t key, uint32_t steps) {
+  const uint32_t g = key >= steps ? 1u : steps / (key ? key : 1u);
+  return 64u * g;
+}
+
+// The plan: keep
+// arrival order if it idles at most 2 % of the lane slots (and no sort is
+// forced), else bucket starts in descending block count.  Bucket rank
+// r = kKeyBins - 1 - key orders buckets longest first; thread t owns ranks
+// 16t .. 16t+15.  Writes the bucket starts (start[key]), the inclusive prefix
+// of queue items per rank (iend[r]) and the queue size.
+constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
+
+__device__ void make_plan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ start,
+                          uint32_t* __restrict__ iend, uint32_t* __restrict__ ctl, uint64_t n,
+                          uint32_t steps, int force_sort, uint32_t* scratch) {
+  __shared__ uint32_t identity;
+  const uint32_t t = threadIdx.x;
+  const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
+  const uint64_t idle = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_IDLE]);
+  const uint64_t avg = useful / (n ? n : 1);
+  if (t == 0) {
+    identity = (!force_sort && idle * 50u <= useful) ? 1u : 0u;
+    ctl[CTL_IDENTITY] = identity;
+    ctl[CTL_PRIO_KEY] = static_cast<uint32_t>(2u * avg + 2u);
+    if (identity) {
+      const uint32_t per = item_msgs(avg > 0xFFFFu ? 0xFFFFu : static_cast<uint32_t>(avg), 8u);
+      ctl[CTL_ID_PER] = per;
+      ctl[CTL_NITEMS] = static_cast<uint32_t>((n + per - 1) / per);
+    }
+  }
+  __syncthreads();
+  if (identity) return;
+  uint32_t cnt[kRanksPerThread], items[kRanksPerThread], c_sum = 0, it_sum = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kRanksPerThread; ++q) {
+    const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
+    cnt[q] = key ? hist[key] : 0u;
+    const uint32_t per = item_msgs(key, steps);
+    items[q] = (cnt[q] + per - 1u) / per;
+    c_sum += cnt[q];
+    it_sum += items[q];
+  }
+  uint32_t c_base = block_inclusive_scan(c_sum, scratch) - c_sum;
+  uint32_t it_run = block_inclusive_scan(it_sum, scratch) - it_sum;
+#pragma unroll
+  for (uint32_t q = 0; q < kRanksPerThread; ++q) {
+    const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
+    start[key] = c_base;
+    c_base += cnt[q];
+    it_run += items[q];
+    iend[kRanksPerThread * t + q] = it_run;
+  }
+  if (t == kBlock - 1) ctl[CTL_NITEMS] = it_run;
+}
+
+// One workgroup makes the plan once the histogram is complete.  (Folding
+// this into the last workgroup of k_count costs more than the launch: every
+// workgroup must then fence and wait for its histogram atomics before
+// drawing a ticket.)
+__global__ __launch_bounds__(kBlock) void k_plan(const uint32_t* __restrict__ hist,
+                                                 uint32_t* __restrict__ start,
+                                                 uint32_t* __restrict__ iend,
+                                                 uint32_t* __restrict__ ctl, uint64_t n,
+                                                 uint32_t steps, int force_sort) {
+  __shared__ uint32_t scratch[kBlock];
+  make_plan(hist, start, iend, ctl, n, steps, force_sort, scratch);
+}
+
 // Histogram of block-count keys and the lane slots arrival order would
-// idle.  A wave takes kCountUnroll consecutive 64-message chunks per pass,
-// issuing all their length loads before using any.  When all 64 messages of
-// a chunk share one key (the common case for uniform batches) one LDS atomic
-// records them; otherwise every lane adds its own key and the chunk's idle
-// slots (count * max - sum) are accumulated.
+// idle.  A wave takes kCountUnroll whole 64-message chunks per pass and
+// issues all their length loads before using any; the chunks past the last
+// whole pass (and the ragged last chunk) are taken one at a time with bounds
+// checks.
 constexpr int kCountUnroll = 8;
 
 template <int V>
@@ -440,36 +609,28 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ l
   const uint64_t wave_id = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
   uint64_t useful = 0, idle = 0;
   uint32_t kmax = 0;
-  for (uint64_t c0 = wave_id * kCountUnroll; c0 * 64u < n; c0 += waves * kCountUnroll) {
+  const uint64_t passes = (n / 64u) / kCountUnroll;  // passes of whole chunks
+  for (uint64_t g = wave_id; g < passes; g += waves) {
     uint64_t len[kCountUnroll];
     int var[kCountUnroll];
 #pragma unroll
     for (int u = 0; u < kCountUnroll; ++u) {
-      const uint64_t i = (c0 + u) * 64u + lane;
-      len[u] = i < n ? lens[i] : 0u;
+      const uint64_t i = (g * kCountUnroll + u) * 64u + lane;
+      len[u] = lens[i];
       var[u] = V;
-      if constexpr (V == kMixed) var[u] = i < n ? vars[i] : 0;
+      if constexpr (V == kMixed) var[u] = vars[i];
     }
 #pragma unroll
-    for (int u = 0; u < kCountUnroll; ++u) {
-      const uint64_t c = c0 + u;
-      if (c * 64u >= n) break;
-      const uint64_t i = c * 64u + lane;
-      const bool valid = i < n;
-      const uint32_t key = valid ? key_of(blocks_of<V>(len[u], var[u])) : 0u;
-      const uint32_t key0 = __builtin_amdgcn_readfirstlane(key);  // lane 0 is always valid
-      kmax = key > kmax ? key : kmax;
-      const uint64_t cnt = n - c * 64u < 64u ? n - c * 64u : 64u;
-      if (__ballot(valid && key != key0) == 0) {
-        if (lane == 0) atomicAdd(&lhist[key0], static_cast<uint32_t>(cnt));
-        useful += static_cast<uint64_t>(key0) * cnt;
-      } else {
-        if (valid) atomicAdd(&lhist[key], 1u);
-        const uint32_t sm = wave_sum(key), mx = wave_max(key);
-        useful += sm;
-        idle += static_cast<uint64_t>(mx) * cnt - sm;
-      }
-    }
+    for (int u = 0; u < kCountUnroll; ++u)
+      count_chunk<V>(len[u], var[u], true, 64u, lane, lhist, useful, idle, kmax);
+  }
+  for (uint64_t c = passes * kCountUnroll + wave_id; c * 64u < n; c += waves) {
+    const uint64_t i = c * 64u + lane;
+    const bool valid = i < n;
+    const uint64_t len = valid ? lens[i] : 0u;
+    const int var = V == kMixed ? (valid ? vars[i] : 0) : V;
+    const uint32_t cnt = n - c * 64u < 64u ? static_cast<uint32_t>(n - c * 64u) : 64u;
+    count_chunk<V>(len, var, valid, cnt, lane, lhist, useful, idle, kmax);
   }
   if (lane == 0) {
     atomicAdd(&luseful, static_cast<unsigned long long>(useful));
@@ -483,81 +644,6 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ l
     atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_USEFUL]), luseful);
     atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_IDLE]), lidle);
     atomicMax(&ctl[CTL_MAXKEY], lmax);
-  }
-}
-
-// Block-wide inclusive scan of one value per thread (kPlanThreads threads).
-__device__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* scratch) {
-  const uint32_t t = threadIdx.x;
-  scratch[t] = v;
-  __syncthreads();
-  for (uint32_t d = 1; d < kPlanThreads; d <<= 1) {
-    const uint32_t add = t >= d ? scratch[t - d] : 0u;
-    __syncthreads();
-    scratch[t] += add;
-    __syncthreads();
-  }
-  const uint32_t r = scratch[t];
-  __syncthreads();
-  return r;
-}
-
-// Messages per queue item in a bucket of `key` blocks: 64 lanes times enough
-// messages per lane to give about `steps` permutations per lane.
-__device__ __forceinline__ uint32_t item_msgs(uint32_t key, uint32_t steps) {
-  const uint32_t g = key >= steps ? 1u : steps / (key ? key : 1u);
-  return 64u * g;
-}
-
-// One workgroup of kPlanThreads threads.  Bucket rank r = kKeyBins - 1 - key
-// orders buckets longest first; thread t owns ranks 4t .. 4t+3.  Writes the
-// bucket starts (start[key]) and the inclusive prefix of queue items per rank
-// (iend[r]).
-__global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restrict__ hist,
-                                                       uint32_t* __restrict__ start,
-                                                       uint32_t* __restrict__ iend,
-                                                       uint32_t* __restrict__ ctl, uint64_t n,
-                                                       uint32_t steps, int force_sort) {
-  __shared__ uint32_t scratch[kPlanThreads];
-  __shared__ uint32_t identity;
-  const uint32_t t = threadIdx.x;
-  if (t == 0) {
-    const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
-    const uint64_t idle = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_IDLE]);
-    identity = (!force_sort && idle * 50u <= useful) ? 1u : 0u;
-    ctl[CTL_IDENTITY] = identity;
-    if (identity) {
-      const uint64_t avg = useful / (n ? n : 1);
-      const uint32_t per = item_msgs(avg > 0xFFFFu ? 0xFFFFu : static_cast<uint32_t>(avg), 8u);
-      ctl[CTL_ID_PER] = per;
-      ctl[CTL_NITEMS] = static_cast<uint32_t>((n + per - 1) / per);
-    }
-  }
-  __syncthreads();
-  if (identity) return;
-  uint32_t cnt[4], items[4], c_sum = 0, it_sum = 0;
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t key = kKeyBins - 1u - (4u * t + q);
-    cnt[q] = key ? hist[key] : 0u;
-    const uint32_t per = item_msgs(key, steps);
-    items[q] = (cnt[q] + per - 1u) / per;
-    c_sum += cnt[q];
-    it_sum += items[q];
-  }
-  uint32_t c_base = block_inclusive_scan(c_sum, scratch) - c_sum;
-  uint32_t it_run = block_inclusive_scan(it_sum, scratch) - it_sum;
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t key = kKeyBins - 1u - (4u * t + q);
-    start[key] = c_base;
-    c_base += cnt[q];
-    it_run += items[q];
-    iend[4u * t + q] = it_run;
-  }
-  if (t == kPlanThreads - 1) {
-    ctl[CTL_NITEMS] = it_run;
-    const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
-    const uint64_t avg = useful / (n ? n : 1);
-    ctl[CTL_PRIO_KEY] = static_cast<uint32_t>(2u * avg + 2u);
   }
 }
 
@@ -847,14 +933,18 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, h
   if (rc) return rc;
   hipLaunchKernelGGL(k_reset, dim3(16), dim3(256), 0, s, w.meta, kMetaWords);
   KB_HIP(hipGetLastError());
-  // about 4 passes of 4 waves x kCountUnroll chunks per workgroup, at most 4
-  // workgroups per CU
-  uint64_t cblocks = (b.n + 64 * 16 * kCountUnroll - 1) / (64 * 16 * kCountUnroll);
-  if (cblocks > static_cast<uint64_t>(4 * cus)) cblocks = 4 * cus;
+  // about 2 passes of 4 waves x kCountUnroll chunks per workgroup, at most 2
+  // workgroups per CU: every workgroup ends with the same few global atomics
+  // (one histogram bin in a uniform batch, the control words), which
+  // serialise, so fewer and longer workgroups finish sooner (64 us rather
+  // than 105 us for 2^24 lengths at 8 per CU)
+  const uint64_t per_wg = 64ull * 4 * kCountUnroll * 2;
+  uint64_t cblocks = (b.n + per_wg - 1) / per_wg;
+  if (cblocks > static_cast<uint64_t>(2 * cus)) cblocks = 2 * cus;
   hipLaunchKernelGGL(k_count<V>, dim3(static_cast<uint32_t>(cblocks)), dim3(kBlock), 0, s, b.lens,
                      b.vars, b.n, hist, ctl);
   KB_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, hist, start, iend, ctl, b.n, steps,
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kBlock), 0, s, hist, start, iend, ctl, b.n, steps,
                      force_sort);
   KB_HIP(hipGetLastError());
   const uint64_t iblocks = (max_items(b.n) + kBlock - 1) / kBlock;
@@ -974,19 +1064,32 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
   Workspace* w = own;
   int rc = own ? KB_OK : get_ws(s, 0, lv.off[L] + D, &w);
   if (rc) return rc;
+  // The leaves and the first 8 levels in 256-thread workgroups; more such
+  // launches while over kTreeTop nodes remain; then one kTreeTop-thread
+  // workgroup reduces the rest.  The root is written by whichever launch
+  // produces level L (the leaf launch itself for a single leaf).
   int first = 0;
   do {
-    const int levels = L - first < 8 ? L - first : 8;
-    const uint64_t blocks = (lv.m[first] + kBlock - 1) / kBlock;
-    {
-      TimedLaunch tl(s);
-      hipLaunchKernelGGL(k_tree<V>, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data,
-                         total, leaf, w->tree, first, levels, lv);
+    if (first == 0 || lv.m[first] > static_cast<uint64_t>(kTreeTop)) {
+      const int levels = L - first < 8 ? L - first : 8;
+      const uint64_t blocks = (lv.m[first] + kBlock - 1) / kBlock;
+      {
+        TimedLaunch tl(s);
+        hipLaunchKernelGGL((k_tree<V, kBlock, kb::kPrefetch<V>>), dim3(static_cast<uint32_t>(blocks)),
+                           dim3(kBlock), 0, s, data, total, leaf, w->tree, root, first, levels, L, lv);
+      }
+      KB_HIP(hipGetLastError());
+      first += levels;
+    } else {
+      {
+        TimedLaunch tl(s);
+        hipLaunchKernelGGL((k_tree<V, kTreeTop, false>), dim3(1), dim3(kTreeTop), 0, s, data, total,
+                           leaf, w->tree, root, first, L - first, L, lv);
+      }
+      KB_HIP(hipGetLastError());
+      first = L;
     }
-    KB_HIP(hipGetLastError());
-    first += levels;
   } while (first < L);
-  KB_HIP(hipMemcpyAsync(root, w->tree + lv.off[L], D, hipMemcpyDeviceToDevice, s));
   return KB_OK;
 }
 

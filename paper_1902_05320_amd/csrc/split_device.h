@@ -116,9 +116,13 @@ __device__ __forceinline__ void split_round(Lane (&a)[5], const SplitLane& L, in
     a[j].lo = b[j].lo ^ (~b[(j + 1) % 5].lo & b[(j + 2) % 5].lo);
     a[j].hi = b[j].hi ^ (~b[(j + 1) % 5].hi & b[(j + 2) % 5].hi);
   }
-  // iota (eqs. 8-9)
-  if (kRC.lo[r]) a[0].lo ^= L.iota & kRC.lo[r];
-  if (kRC.hi[r]) a[0].hi ^= L.iota & kRC.hi[r];
+  // iota (eqs. 8-9).  The lane mask passes through an empty asm so that the
+  // 37 masked round constants are formed round by round instead of being
+  // hoisted out of the block loop into as many registers.
+  uint32_t m = L.iota;
+  __asm__ volatile("" : "+v"(m));
+  if (kRC.lo[r]) a[0].lo ^= m & kRC.lo[r];
+  if (kRC.hi[r]) a[0].hi ^= m & kRC.hi[r];
   // back to the diagonal layout through LDS
 #pragma unroll
   for (int j = 0; j < 5; ++j)

@@ -187,6 +187,22 @@ def test_merkle_small_trees(kb, o2, v):
     assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], np.zeros(0, np.uint8), 64)
 
 
+@pytest.mark.parametrize("v", [1, 3])
+def test_merkle_deep_trees(kb, o2, v):
+    # more than 2^18 leaves: more than 1024 nodes remain after the leaf
+    # launch's 8 levels, so a middle launch runs before the last workgroup;
+    # odd counts at most levels carry unpaired nodes up
+    import torch
+    rng = np.random.Generator(np.random.PCG64(60 + v))
+    for n_leaves, leaf in ((300_001, 1), (2**19 + 3, 5)):
+        data = rng.integers(0, 256, n_leaves * leaf - 2 if leaf > 2 else n_leaves * leaf,
+                            dtype=np.uint8)
+        _say("merkle deep", v, n_leaves, leaf, data.size)
+        got = kb.merkle_root(v, torch.from_numpy(data).cuda(), leaf)
+        torch.cuda.synchronize()
+        assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], data, leaf)
+
+
 # --------------------------------------------------------------------------
 # Full-size workloads, in the launch configuration the benchmark times
 # --------------------------------------------------------------------------
