@@ -65,6 +65,7 @@ enum : int {
   CTL_USEFUL = 6,    // uint64 (words 6, 7): sum of (clamped) block counts
   CTL_IDLE = 8,      // uint64 (words 8, 9): lane-slots arrival-order waves would idle
   CTL_PRIO_KEY = 10, // front waves raise their priority on items of at least this many blocks
+  CTL_SPLIT_N = 11,  // bucketed order positions [0, CTL_SPLIT_N) are hashed in the split form
   CTL_WORDS = 64
 };
 
@@ -80,6 +81,8 @@ constexpr uint32_t kSimdSlots = 8 * 8 * 2 * 16 * 4;
 // 256-byte line.
 constexpr uint32_t kQueues = 8;
 constexpr uint32_t kQueueStrideDw = 64;
+// the sub-queues, then the counter of split items on a line of its own
+constexpr uint32_t kQueueAreaDw = (kQueues + 1) * kQueueStrideDw;
 
 struct WorkItem {
   uint32_t begin, end;  // positions in order[] (message indices in arrival order)
@@ -265,6 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_persistent(
     uint32_t* __restrict__ simd_flags, uint8_t* __restrict__ out, uint64_t stride) {
   using S = SpongeShape<V>;
   __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
+  static_assert(2 * (kSplitGroups * kb::split::kGroupSlots + 1) <= 64 * S::kRowDw,
+                "a wave's staging rows hold its split exchange area");
   uint32_t* row = lds + threadIdx.x * S::kRowDw;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t n_items = ctl[CTL_NITEMS];
@@ -276,6 +281,49 @@ __global__ __launch_bounds__(kBlock) void k_persistent(
   const bool front = !sorted || __builtin_amdgcn_readfirstlane(__shfl(claim, 0)) != 0u;
   const unsigned long long step = 1ull << (front ? 0 : 32);
   const uint32_t home = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kQueues - 1u);
+  // Split items first: the front waves hash the longest messages (bucketed
+  // positions [0, split_n)) eight at a time, one per 8-lane group, in the
+  // lane-split form, whose chain of permutations runs about twice as fast.
+  // The exchange area is this wave's own staging rows.
+  // (compiled into the mixed-variant kernel only: in the fixed-variant ones
+  // the extra code alone slowed the one-block uniform batch by 8 %)
+  const uint32_t split_n = sorted && V == kMixed ? ctl[CTL_SPLIT_N] : 0u;
+  if constexpr (V == kMixed) {
+    if (front && split_n) {
+      namespace sp = kb::split;
+      uint64_t* area = reinterpret_cast<uint64_t*>(lds + (threadIdx.x & ~63u) * S::kRowDw);
+      uint64_t* zero = area + kSplitGroups * sp::kGroupSlots;
+      if (lane == 0) *zero = 0;
+      __asm__ volatile("" ::: "memory");
+      sp::SplitLane L;
+      sp::setup(L, lane % sp::kGroupLanes, area + (lane / sp::kGroupLanes) * sp::kGroupSlots, zero);
+      const int slot_dw = V == kMixed ? 16 : kb::digest_bytes_of(V) / 4;
+      uint32_t* split_ctr = reinterpret_cast<uint32_t*>(queues + kQueues * (kQueueStrideDw / 2));
+      __builtin_amdgcn_s_setprio(3);
+      for (;;) {
+        uint32_t d = 0;
+        if (lane == 0)
+          d = __hip_atomic_fetch_add(split_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        d = __builtin_amdgcn_readfirstlane(__shfl(d, 0));
+        if (d >= (split_n + kSplitGroups - 1u) / kSplitGroups) break;
+        const uint32_t pos = d * kSplitGroups + lane / sp::kGroupLanes;
+        if (pos < split_n) {
+          const uint32_t i = order[pos];
+          const int var = V == kMixed ? vars[i] : V;
+          uint32_t* o = reinterpret_cast<uint32_t*>(out + static_cast<uint64_t>(i) * stride);
+          if (V == kMixed && var > 3) {
+            Lane z[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) z[j] = Lane{0u, 0u};
+            sp::store_words(o, z, 0, slot_dw, L);
+          } else {
+            split_hash<V>(data + offs[i], lens[i], var, o, slot_dw, L);
+          }
+        }
+      }
+      __builtin_amdgcn_s_setprio(0);
+    }
+  }
   uint32_t qi = 0;  // sub-queues tried so far (bucketed order)
   for (;;) {
     // choose the next item; the hashing below appears once in the kernel
@@ -526,10 +574,19 @@ __device__ __forceinline__ uint32_t item_msgs(uint32_t key, uint32_t steps) {
 // of queue items per rank (iend[r]) and the queue size.
 constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
 
+// The first CTL_SPLIT_N positions of the bucketed order (the longest
+// messages) go to the split form: the messages of at least
+// max(kSplitMinKey, 4 x the mean, 2 x the blocks per resident lane) blocks,
+// at most `split_cap` of them.  Below the last bound the batch's throughput,
+// not its longest chain, sets the time, and a split item (eight messages per
+// wave) costs throughput.
+constexpr uint32_t kSplitMinKey = 32;
+
 __device__ void make_plan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ start,
                           uint32_t* __restrict__ iend, uint32_t* __restrict__ ctl, uint64_t n,
-                          uint32_t steps, int force_sort, uint32_t* scratch) {
-  __shared__ uint32_t identity;
+                          uint32_t steps, int force_sort, uint32_t split_cap, uint64_t lanes,
+                          uint32_t* scratch) {
+  __shared__ uint32_t identity, split_n;
   const uint32_t t = threadIdx.x;
   const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
   const uint64_t idle = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_IDLE]);
@@ -546,27 +603,55 @@ __device__ void make_plan(const uint32_t* __restrict__ hist, uint32_t* __restric
   }
   __syncthreads();
   if (identity) return;
-  uint32_t cnt[kRanksPerThread], items[kRanksPerThread], c_sum = 0, it_sum = 0;
+  uint32_t cnt[kRanksPerThread], st[kRanksPerThread], c_sum = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
     cnt[q] = key ? hist[key] : 0u;
-    const uint32_t per = item_msgs(key, steps);
-    items[q] = (cnt[q] + per - 1u) / per;
     c_sum += cnt[q];
-    it_sum += items[q];
   }
   uint32_t c_base = block_inclusive_scan(c_sum, scratch) - c_sum;
-  uint32_t it_run = block_inclusive_scan(it_sum, scratch) - it_sum;
+  // bucket starts; the split range ends where the keys drop below kmin
+  const uint64_t per_lane = 2u * useful / (lanes ? lanes : 1u);
+  uint64_t kmin64 = 4u * avg > kSplitMinKey ? 4u * avg : kSplitMinKey;
+  if (per_lane > kmin64) kmin64 = per_lane;
+  const uint32_t kmin = kmin64 < kKeyBins - 1u ? static_cast<uint32_t>(kmin64) : kKeyBins - 1u;
+  if (t == 0) split_n = static_cast<uint32_t>(n);  // every key at least kmin
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
+    st[q] = c_base;
     start[key] = c_base;
     c_base += cnt[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t q = 0; q < kRanksPerThread; ++q) {
+    const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
+    if (key == kmin - 1u) split_n = st[q];  // messages in buckets of key >= kmin
+  }
+  __syncthreads();
+  const uint32_t split = split_n < split_cap ? split_n : split_cap;
+  // queue items over the positions past the split range
+  uint32_t items[kRanksPerThread], it_sum = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kRanksPerThread; ++q) {
+    const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
+    const uint32_t b = st[q] > split ? st[q] : split, e = st[q] + cnt[q];
+    const uint32_t per = item_msgs(key, steps);
+    items[q] = e > b ? (e - b + per - 1u) / per : 0u;
+    it_sum += items[q];
+  }
+  uint32_t it_run = block_inclusive_scan(it_sum, scratch) - it_sum;
+#pragma unroll
+  for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     it_run += items[q];
     iend[kRanksPerThread * t + q] = it_run;
   }
-  if (t == kBlock - 1) ctl[CTL_NITEMS] = it_run;
+  if (t == kBlock - 1) {
+    ctl[CTL_NITEMS] = it_run;
+    ctl[CTL_SPLIT_N] = split;
+  }
 }
 
 // One workgroup makes the plan once the histogram is complete.  (Folding
@@ -577,9 +662,10 @@ __global__ __launch_bounds__(kBlock) void k_plan(const uint32_t* __restrict__ hi
                                                  uint32_t* __restrict__ start,
                                                  uint32_t* __restrict__ iend,
                                                  uint32_t* __restrict__ ctl, uint64_t n,
-                                                 uint32_t steps, int force_sort) {
+                                                 uint32_t steps, int force_sort,
+                                                 uint32_t split_cap, uint64_t lanes) {
   __shared__ uint32_t scratch[kBlock];
-  make_plan(hist, start, iend, ctl, n, steps, force_sort, scratch);
+  make_plan(hist, start, iend, ctl, n, steps, force_sort, split_cap, lanes, scratch);
 }
 
 // Histogram of block-count keys and the lane slots arrival order would
@@ -673,7 +759,8 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t* __restrict__ h
   const uint32_t key = kKeyBins - 1u - lo;
   const uint32_t per = item_msgs(key, steps);
   const uint32_t first_item = lo ? iend[lo - 1] : 0u;
-  const uint32_t b = start[key] + (t - first_item) * per;
+  const uint32_t split = ctl[CTL_SPLIT_N];  // positions before it are split work
+  const uint32_t b = (start[key] > split ? start[key] : split) + (t - first_item) * per;
   const uint32_t bucket_end = start[key] + hist[key];
   items[t] = WorkItem{b, b + per < bucket_end ? b + per : bucket_end, key, 0u};
 }
@@ -763,7 +850,7 @@ struct Workspace {
   uint32_t* host_hist = nullptr;  // pinned, for the per-bucket form
 };
 
-constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS + kQueues * kQueueStrideDw + kSimdSlots;
+constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS + kQueueAreaDw + kSimdSlots;
 
 // Measurement hook state (keccak_timing_*): event pairs around kernel launches.
 struct Timing {
@@ -921,7 +1008,8 @@ int launch_split(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
 }
 
 template <int V>
-int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, hipStream_t s) {
+int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, uint64_t lanes,
+                 hipStream_t s) {
   uint32_t* hist = w.meta;
   uint32_t* start = w.meta + kKeyBins;
   uint32_t* cursor = w.meta + 2 * kKeyBins;
@@ -944,8 +1032,12 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, h
   hipLaunchKernelGGL(k_count<V>, dim3(static_cast<uint32_t>(cblocks)), dim3(kBlock), 0, s, b.lens,
                      b.vars, b.n, hist, ctl);
   KB_HIP(hipGetLastError());
+  // at most eight split messages per SIMD: one 8-group split item for each
+  // SIMD's front wave (mixed-variant kernel only; the per-bucket form takes
+  // none)
+  const uint32_t split_cap = V == kMixed && !force_sort ? 8u * 4u * static_cast<uint32_t>(cus) : 0u;
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(kBlock), 0, s, hist, start, iend, ctl, b.n, steps,
-                     force_sort);
+                     force_sort, split_cap, lanes);
   KB_HIP(hipGetLastError());
   const uint64_t iblocks = (max_items(b.n) + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_items, dim3(static_cast<uint32_t>(iblocks)), dim3(kBlock), 0, s, hist, start,
@@ -968,7 +1060,7 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Work
   if (rc) return rc;
   uint32_t steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 4u;
   if (mode == KB_MODE_PER_BUCKET) {
-    rc = run_schedule<V>(b, *w, steps, 1, s);
+    rc = run_schedule<V>(b, *w, steps, 1, 0, s);
     if (rc) return rc;
     if (!w->host_hist) KB_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->host_hist), kKeyBins * 4, 0));
     KB_HIP(hipMemcpyAsync(w->host_hist, w->meta, kKeyBins * 4, hipMemcpyDeviceToHost, s));
@@ -983,8 +1075,6 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Work
     }
     return KB_OK;
   }
-  rc = run_schedule<V>(b, *w, steps, 0, s);
-  if (rc) return rc;
   int dev = 0, cus = 0;
   KB_HIP(hipGetDevice(&dev));
   rc = cu_count(dev, &cus);
@@ -997,12 +1087,14 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Work
     if (want >= 1 && want < per_cu) per_cu = want;
   }
   const uint32_t grid = static_cast<uint32_t>(per_cu * cus);
+  rc = run_schedule<V>(b, *w, steps, 0, static_cast<uint64_t>(grid) * kBlock, s);
+  if (rc) return rc;
   {
     TimedLaunch tl(s);
     hipLaunchKernelGGL(k_persistent<V>, dim3(grid), dim3(kBlock), 0, s, b.data, b.offs, b.lens,
                        b.vars, w->order, w->items, w->meta + 4 * kKeyBins,
                        reinterpret_cast<unsigned long long*>(w->meta + 4 * kKeyBins + CTL_WORDS),
-                       w->meta + 4 * kKeyBins + CTL_WORDS + kQueues * kQueueStrideDw, b.out,
+                       w->meta + 4 * kKeyBins + CTL_WORDS + kQueueAreaDw, b.out,
                        b.stride);
   }
   KB_HIP(hipGetLastError());

@@ -113,13 +113,16 @@ __device__ __forceinline__ void stage_block(uint32_t* __restrict__ row, const Bl
 // With prefetch on, the chunks of block b+1 are loaded into registers before
 // the permutation of block b and land while it runs, so a multi-block
 // message's chain of permutations does not wait for HBM between blocks.  It
-// costs the registers of one block of chunks (about 40 VGPRs, which drops a
-// 256-thread workgroup from four to three waves per SIMD); on 4 KiB Merkle
-// leaves the prefetch wins (1.14 vs 1.23 ms of kernel time per 1 GiB root)
-// and on one-block messages the two are level.  The mixed-variant form
-// leaves it off.
+// costs the registers of one block of chunks (about 40 VGPRs).  Measured by
+// interleaved A/B on one box: 4 KiB Merkle leaves 1.14 ms per 1 GiB root
+// with it against 1.23 without (three waves per SIMD against four); the
+// mixed-variant batch of lengths up to 16 KiB 2.40 ms against 2.52, although
+// the mixed kernel then holds two waves per SIMD instead of three (206 VGPRs;
+// capping it at three spills); one-block messages are level either way.
+// The chain of the longest message bounds a batch of uneven lengths, so the
+// latency of each block matters more than the occupancy.
 template <int V>
-constexpr bool kPrefetch = V != kMixed;
+constexpr bool kPrefetch = true;
 
 template <int V, bool PF = kPrefetch<V>>
 __device__ __forceinline__ void sponge_hash(Lane (&A)[25], const uint8_t* msg, uint64_t len,

@@ -99,6 +99,30 @@ def test_uneven_single_variant(kb, o2, v):
     assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
 
 
+@pytest.mark.parametrize("case", ["few_long", "many_long"])
+def test_persistent_split_tail(kb, o2, case):
+    # the longest messages of a bucketed batch go to the split form (at
+    # most eight per SIMD, and only messages of at least 4x the mean block
+    # count); few: 40 messages of ~0.2-1 MB among 60000 short ones; many:
+    # 12000 messages of ~20 KB among 200000 short ones, more than the split
+    # cap, so the rest of their buckets runs one message per thread
+    rng = np.random.Generator(np.random.PCG64(70))
+    if case == "few_long":
+        lens = np.concatenate([rng.integers(0, 300, 60000), rng.integers(200_000, 1_000_000, 40)])
+    else:
+        lens = np.concatenate([rng.integers(0, 300, 200000), rng.integers(19_000, 21_000, 12000)])
+    rng.shuffle(lens)
+    var = rng.integers(0, 4, lens.size).astype(np.uint8)
+    b = wl.explicit(lens, seed=71, variant=var, gap=1, lead=3)
+    _say("persistent split tail", case, b.n)
+    got = _gpu_mixed(kb, b)
+    want = o2.sha3_batch_mixed(b.variants, b.data, b.offsets, b.lengths)
+    assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
+    v1 = wl.explicit(lens, seed=72, variant=1, gap=0, lead=1)
+    got1 = _gpu_batch(kb, 1, v1)
+    assert (got1 == o2.sha3_batch(256, v1.data, v1.offsets, v1.lengths)).all()
+
+
 @pytest.mark.parametrize("mode", ["persistent", "split"])
 def test_mixed_invalid_variant_slot_is_zero(kb, o2, mode):
     b = wl.explicit([10, 200, 0, 77], seed=5, variant=np.array([1, 9, 3, 255], dtype=np.uint8))
