@@ -259,8 +259,10 @@ def bench_serving(args, kbatch, workloads, torch, dev):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    # the GPU's clock ramps over the first dozen or so 2-ms steps of a fresh
+    # process (kernel time falls from ~2.0 to ~1.7 ms); warm up past that
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -347,7 +349,7 @@ def main():
 
     plain = None
     if not args.no_plain:
-        for _ in range(2):
+        for _ in range(args.warmup):
             step("plain")
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -84,6 +84,17 @@ constexpr uint32_t kQueueStrideDw = 64;
 // the sub-queues, then the counter of split items on a line of its own
 constexpr uint32_t kQueueAreaDw = (kQueues + 1) * kQueueStrideDw;
 
+// k_count accumulates into kCopies partial histograms and control sums (copy
+// = workgroup index mod 8, which is its XCD), so that the workgroups' closing
+// atomics spread over eight addresses instead of one; k_plan folds them.
+constexpr uint32_t kCopies = 8;
+constexpr uint32_t kPartialWords = 8;  // per copy: useful (u64), idle (u64), max key
+enum : uint32_t { P_USEFUL = 0, P_IDLE = 2, P_MAXKEY = 4 };
+// Workspace metadata layout (uint32 words): hist | start | cursor | iend |
+// ctl | queues | SIMD flags | hist copies 1..7 | partials.
+constexpr uint32_t kHistCopiesOff = 4 * kKeyBins + CTL_WORDS + kQueueAreaDw + kSimdSlots;
+constexpr uint32_t kPartialsOff = kHistCopiesOff + (kCopies - 1) * kKeyBins;
+
 struct WorkItem {
   uint32_t begin, end;  // positions in order[] (message indices in arrival order)
   uint32_t key;         // block-count bucket of the item (0 in arrival order)
@@ -582,14 +593,27 @@ constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
 // wave) costs throughput.
 constexpr uint32_t kSplitMinKey = 32;
 
-__device__ void make_plan(const uint32_t* __restrict__ hist, uint32_t* __restrict__ start,
+__device__ void make_plan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ hist_copies,
+                          const uint32_t* __restrict__ partials, uint32_t* __restrict__ start,
                           uint32_t* __restrict__ iend, uint32_t* __restrict__ ctl, uint64_t n,
                           uint32_t steps, int force_sort, uint32_t split_cap, uint64_t lanes,
                           uint32_t* scratch) {
   __shared__ uint32_t identity, split_n;
   const uint32_t t = threadIdx.x;
-  const uint64_t useful = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_USEFUL]);
-  const uint64_t idle = *reinterpret_cast<const unsigned long long*>(&ctl[CTL_IDLE]);
+  uint64_t useful = 0, idle = 0;
+  uint32_t maxkey = 0;
+#pragma unroll
+  for (uint32_t c = 0; c < kCopies; ++c) {
+    const uint32_t* pc = partials + c * kPartialWords;
+    useful += *reinterpret_cast<const unsigned long long*>(pc + P_USEFUL);
+    idle += *reinterpret_cast<const unsigned long long*>(pc + P_IDLE);
+    maxkey = pc[P_MAXKEY] > maxkey ? pc[P_MAXKEY] : maxkey;
+  }
+  if (t == 0) {
+    *reinterpret_cast<unsigned long long*>(&ctl[CTL_USEFUL]) = useful;
+    *reinterpret_cast<unsigned long long*>(&ctl[CTL_IDLE]) = idle;
+    ctl[CTL_MAXKEY] = maxkey;
+  }
   const uint64_t avg = useful / (n ? n : 1);
   if (t == 0) {
     identity = (!force_sort && idle * 50u <= useful) ? 1u : 0u;
@@ -607,7 +631,11 @@ __device__ void make_plan(const uint32_t* __restrict__ hist, uint32_t* __restric
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
-    cnt[q] = key ? hist[key] : 0u;
+    uint32_t c = hist[key];
+#pragma unroll
+    for (uint32_t k = 1; k < kCopies; ++k) c += hist_copies[(k - 1) * kKeyBins + key];
+    hist[key] = c;  // the folded histogram, read by k_items and the per-bucket form
+    cnt[q] = key ? c : 0u;
     c_sum += cnt[q];
   }
   uint32_t c_base = block_inclusive_scan(c_sum, scratch) - c_sum;
@@ -658,28 +686,68 @@ __device__ void make_plan(const uint32_t* __restrict__ hist, uint32_t* __restric
 // this into the last workgroup of k_count costs more than the launch: every
 // workgroup must then fence and wait for its histogram atomics before
 // drawing a ticket.)
-__global__ __launch_bounds__(kBlock) void k_plan(const uint32_t* __restrict__ hist,
+__global__ __launch_bounds__(kBlock) void k_plan(uint32_t* __restrict__ hist,
+                                                 const uint32_t* __restrict__ hist_copies,
+                                                 const uint32_t* __restrict__ partials,
                                                  uint32_t* __restrict__ start,
                                                  uint32_t* __restrict__ iend,
                                                  uint32_t* __restrict__ ctl, uint64_t n,
                                                  uint32_t steps, int force_sort,
                                                  uint32_t split_cap, uint64_t lanes) {
   __shared__ uint32_t scratch[kBlock];
-  make_plan(hist, start, iend, ctl, n, steps, force_sort, split_cap, lanes, scratch);
+  make_plan(hist, hist_copies, partials, start, iend, ctl, n, steps, force_sort, split_cap, lanes,
+            scratch);
+}
+
+// Two 64-message chunks of arrival order, messages 2 lane and 2 lane + 1 of
+// a 128-message pair in each lane (lanes 0-31 hold the first chunk, 32-63
+// the second).  Same accounting as count_chunk, with one LDS atomic for the
+// pair when all 128 lengths and variants are equal.
+template <int V>
+__device__ __forceinline__ void count_pair(uint64_t la, uint64_t lb, int va, int vb, uint32_t lane,
+                                           uint32_t* lhist, uint64_t& useful, uint64_t& idle,
+                                           uint32_t& kmax) {
+  const uint32_t lo0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(la));
+  const uint32_t hi0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(la >> 32));
+  const uint64_t len0 = (static_cast<uint64_t>(hi0) << 32) | lo0;
+  const int var0 = V == kMixed ? __builtin_amdgcn_readfirstlane(va) : V;
+  if (__ballot(la != len0 || lb != len0 || va != var0 || vb != var0) == 0) {
+    const uint32_t key = key_of(blocks_of<V>(len0, var0));
+    if (lane == 0) atomicAdd(&lhist[key], 128u);
+    useful += static_cast<uint64_t>(key) * 128u;
+    kmax = key > kmax ? key : kmax;
+  } else {
+    const uint32_t ka = key_of(blocks_of<V>(la, va)), kb = key_of(blocks_of<V>(lb, vb));
+    atomicAdd(&lhist[ka], 1u);
+    atomicAdd(&lhist[kb], 1u);
+    uint32_t sm = ka + kb, mx = ka > kb ? ka : kb;
+    kmax = mx > kmax ? mx : kmax;
+    for (int d = 16; d >= 1; d >>= 1) {  // within each half of the wave
+      sm += __shfl_xor(sm, d);
+      const uint32_t o = __shfl_xor(mx, d);
+      mx = o > mx ? o : mx;
+    }
+    const uint32_t s0 = __builtin_amdgcn_readlane(sm, 0), s1 = __builtin_amdgcn_readlane(sm, 32);
+    const uint32_t m0 = __builtin_amdgcn_readlane(mx, 0), m1 = __builtin_amdgcn_readlane(mx, 32);
+    useful += static_cast<uint64_t>(s0) + s1;
+    idle += (64ull * m0 - s0) + (64ull * m1 - s1);
+  }
 }
 
 // Histogram of block-count keys and the lane slots arrival order would
-// idle.  A wave takes kCountUnroll whole 64-message chunks per pass and
-// issues all their length loads before using any; the chunks past the last
-// whole pass (and the ragged last chunk) are taken one at a time with bounds
-// checks.
+// idle, into copy blockIdx.x mod kCopies of the histogram and the control
+// partials.  A wave takes kCountUnroll whole 128-message pairs per pass, two
+// adjacent lengths per lane, and issues all their loads before using any;
+// the chunks past the last whole pass (and the ragged last chunk) are taken
+// one at a time with bounds checks.
 constexpr int kCountUnroll = 8;
 
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ lens,
                                                   const uint8_t* __restrict__ vars, uint64_t n,
                                                   uint32_t* __restrict__ hist,
-                                                  uint32_t* __restrict__ ctl) {
+                                                  uint32_t* __restrict__ hist_copies,
+                                                  uint32_t* __restrict__ partials) {
   __shared__ uint32_t lhist[kKeyBins];
   __shared__ unsigned long long luseful, lidle;
   __shared__ uint32_t lmax;
@@ -695,22 +763,26 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ l
   const uint64_t wave_id = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
   uint64_t useful = 0, idle = 0;
   uint32_t kmax = 0;
-  const uint64_t passes = (n / 64u) / kCountUnroll;  // passes of whole chunks
+  const uint64_t passes = (n / 128u) / kCountUnroll;  // passes of whole pairs
   for (uint64_t g = wave_id; g < passes; g += waves) {
-    uint64_t len[kCountUnroll];
-    int var[kCountUnroll];
+    uint64_t la[kCountUnroll], lb[kCountUnroll];
+    int va[kCountUnroll], vb[kCountUnroll];
 #pragma unroll
     for (int u = 0; u < kCountUnroll; ++u) {
-      const uint64_t i = (g * kCountUnroll + u) * 64u + lane;
-      len[u] = lens[i];
-      var[u] = V;
-      if constexpr (V == kMixed) var[u] = vars[i];
+      const uint64_t i = (g * kCountUnroll + u) * 128u + 2u * lane;
+      la[u] = lens[i];
+      lb[u] = lens[i + 1];
+      va[u] = vb[u] = V;
+      if constexpr (V == kMixed) {
+        va[u] = vars[i];
+        vb[u] = vars[i + 1];
+      }
     }
 #pragma unroll
     for (int u = 0; u < kCountUnroll; ++u)
-      count_chunk<V>(len[u], var[u], true, 64u, lane, lhist, useful, idle, kmax);
+      count_pair<V>(la[u], lb[u], va[u], vb[u], lane, lhist, useful, idle, kmax);
   }
-  for (uint64_t c = passes * kCountUnroll + wave_id; c * 64u < n; c += waves) {
+  for (uint64_t c = passes * kCountUnroll * 2u + wave_id; c * 64u < n; c += waves) {
     const uint64_t i = c * 64u + lane;
     const bool valid = i < n;
     const uint64_t len = valid ? lens[i] : 0u;
@@ -724,12 +796,15 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ l
   }
   atomicMax(&lmax, kmax);
   __syncthreads();
+  const uint32_t copy = blockIdx.x % kCopies;
+  uint32_t* h = copy ? hist_copies + (copy - 1u) * kKeyBins : hist;
   for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock)
-    if (lhist[k]) atomicAdd(&hist[k], lhist[k]);
+    if (lhist[k]) atomicAdd(&h[k], lhist[k]);
   if (threadIdx.x == 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_USEFUL]), luseful);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&ctl[CTL_IDLE]), lidle);
-    atomicMax(&ctl[CTL_MAXKEY], lmax);
+    uint32_t* pc = partials + copy * kPartialWords;
+    atomicAdd(reinterpret_cast<unsigned long long*>(pc + P_USEFUL), luseful);
+    atomicAdd(reinterpret_cast<unsigned long long*>(pc + P_IDLE), lidle);
+    atomicMax(pc + P_MAXKEY, lmax);
   }
 }
 
@@ -850,7 +925,7 @@ struct Workspace {
   uint32_t* host_hist = nullptr;  // pinned, for the per-bucket form
 };
 
-constexpr uint32_t kMetaWords = 4 * kKeyBins + CTL_WORDS + kQueueAreaDw + kSimdSlots;
+constexpr uint32_t kMetaWords = kPartialsOff + kCopies * kPartialWords;
 
 // Measurement hook state (keccak_timing_*): event pairs around kernel launches.
 struct Timing {
@@ -1019,25 +1094,25 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, u
   KB_HIP(hipGetDevice(&dev));
   int rc = cu_count(dev, &cus);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_reset, dim3(16), dim3(256), 0, s, w.meta, kMetaWords);
+  hipLaunchKernelGGL(k_reset, dim3(64), dim3(256), 0, s, w.meta, kMetaWords);
   KB_HIP(hipGetLastError());
-  // about 2 passes of 4 waves x kCountUnroll chunks per workgroup, at most 2
-  // workgroups per CU: every workgroup ends with the same few global atomics
-  // (one histogram bin in a uniform batch, the control words), which
-  // serialise, so fewer and longer workgroups finish sooner (64 us rather
-  // than 105 us for 2^24 lengths at 8 per CU)
-  const uint64_t per_wg = 64ull * 4 * kCountUnroll * 2;
+  // about 2 passes of 4 waves x kCountUnroll 128-message pairs per workgroup,
+  // at most 2 workgroups per CU: the workgroups' closing atomics serialise per
+  // address, so fewer, longer workgroups finish sooner (on 2^24 lengths the
+  // whole schedule costs 48 us at 2 per CU, 54 at 4 and 65 at 8)
+  const uint64_t per_wg = 128ull * 4 * kCountUnroll * 2;
   uint64_t cblocks = (b.n + per_wg - 1) / per_wg;
   if (cblocks > static_cast<uint64_t>(2 * cus)) cblocks = 2 * cus;
   hipLaunchKernelGGL(k_count<V>, dim3(static_cast<uint32_t>(cblocks)), dim3(kBlock), 0, s, b.lens,
-                     b.vars, b.n, hist, ctl);
+                     b.vars, b.n, hist, w.meta + kHistCopiesOff, w.meta + kPartialsOff);
   KB_HIP(hipGetLastError());
   // at most eight split messages per SIMD: one 8-group split item for each
   // SIMD's front wave (mixed-variant kernel only; the per-bucket form takes
   // none)
   const uint32_t split_cap = V == kMixed && !force_sort ? 8u * 4u * static_cast<uint32_t>(cus) : 0u;
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kBlock), 0, s, hist, start, iend, ctl, b.n, steps,
-                     force_sort, split_cap, lanes);
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kBlock), 0, s, hist, w.meta + kHistCopiesOff,
+                     w.meta + kPartialsOff, start, iend, ctl, b.n, steps, force_sort, split_cap,
+                     lanes);
   KB_HIP(hipGetLastError());
   const uint64_t iblocks = (max_items(b.n) + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_items, dim3(static_cast<uint32_t>(iblocks)), dim3(kBlock), 0, s, hist, start,
