@@ -10,9 +10,9 @@
 //               lane slots, else bucket starts in descending nb (longest
 //               first) and queue-item counts per bucket (about
 //               `steps_per_item` permutations per lane each)
-//   k_items     one thread per queue item: its message range and bucket
-//   k_scatter   counting-sort scatter of message indices into `order`
-//               (skipped when arrival order is kept)
+//   k_fill      one thread per queue item: its message range and bucket;
+//               in the same launch, the counting-sort scatter of message
+//               indices into `order` (skipped when arrival order is kept)
 //   k_persistent  a grid sized to the resident capacity pops items from an
 //               atomic counter; each lane hashes one message per step.  The
 //               longest items run at raised wave priority so that the long
@@ -634,7 +634,7 @@ __device__ void make_plan(uint32_t* __restrict__ hist, const uint32_t* __restric
     uint32_t c = hist[key];
 #pragma unroll
     for (uint32_t k = 1; k < kCopies; ++k) c += hist_copies[(k - 1) * kKeyBins + key];
-    hist[key] = c;  // the folded histogram, read by k_items and the per-bucket form
+    hist[key] = c;  // the folded histogram, read by k_fill and the per-bucket form
     cnt[q] = key ? c : 0u;
     c_sum += cnt[q];
   }
@@ -810,12 +810,12 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ l
 
 // Queue item t: its bucket (the smallest rank r with iend[r] > t) and its
 // range of positions in the bucketed order.
-__global__ __launch_bounds__(kBlock) void k_items(const uint32_t* __restrict__ hist,
-                                                  const uint32_t* __restrict__ start,
-                                                  const uint32_t* __restrict__ iend,
-                                                  const uint32_t* __restrict__ ctl, uint64_t n,
-                                                  uint32_t steps, WorkItem* __restrict__ items) {
-  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void items_block(uint32_t blk, const uint32_t* __restrict__ hist,
+                                            const uint32_t* __restrict__ start,
+                                            const uint32_t* __restrict__ iend,
+                                            const uint32_t* __restrict__ ctl, uint64_t n,
+                                            uint32_t steps, WorkItem* __restrict__ items) {
+  const uint32_t t = blk * kBlock + threadIdx.x;
   if (t >= ctl[CTL_NITEMS]) return;
   if (ctl[CTL_IDENTITY]) {
     const uint64_t per = ctl[CTL_ID_PER];
@@ -844,18 +844,18 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t* __restrict__ h
 // reserves one range per non-empty bucket with a single global atomic, and
 // ranks its messages inside each range with LDS atomics.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__ lens,
-                                                    const uint8_t* __restrict__ vars, uint64_t n,
-                                                    const uint32_t* __restrict__ start,
-                                                    uint32_t* __restrict__ cursor,
-                                                    const uint32_t* __restrict__ ctl,
-                                                    uint32_t* __restrict__ order) {
+__device__ __forceinline__ void scatter_block(uint32_t blk, const uint64_t* __restrict__ lens,
+                                              const uint8_t* __restrict__ vars, uint64_t n,
+                                              const uint32_t* __restrict__ start,
+                                              uint32_t* __restrict__ cursor,
+                                              const uint32_t* __restrict__ ctl,
+                                              uint32_t* __restrict__ order) {
   if (ctl[CTL_IDENTITY]) return;
   __shared__ uint32_t lcount[kKeyBins];
   __shared__ uint32_t lbase[kKeyBins];
   for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock) lcount[k] = 0u;
   __syncthreads();
-  const uint64_t first = static_cast<uint64_t>(blockIdx.x) * kScatterTile;
+  const uint64_t first = static_cast<uint64_t>(blk) * kScatterTile;
   const uint64_t last = first + kScatterTile < n ? first + kScatterTile : n;
   uint32_t keys[kScatterTile / kBlock];
 #pragma unroll
@@ -879,6 +879,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t* __restrict__
       order[lbase[keys[q]] + rank] = static_cast<uint32_t>(i);
     }
   }
+}
+
+// Queue items and the scatter in one launch (both depend only on the plan):
+// workgroups [0, iblocks) write queue items, the rest scatter the order.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_fill(const uint64_t* __restrict__ lens,
+                                                 const uint8_t* __restrict__ vars, uint64_t n,
+                                                 const uint32_t* __restrict__ hist,
+                                                 const uint32_t* __restrict__ start,
+                                                 uint32_t* __restrict__ cursor,
+                                                 const uint32_t* __restrict__ iend,
+                                                 const uint32_t* __restrict__ ctl, uint32_t steps,
+                                                 uint32_t iblocks, WorkItem* __restrict__ items,
+                                                 uint32_t* __restrict__ order) {
+  if (blockIdx.x < iblocks)
+    items_block(blockIdx.x, hist, start, iend, ctl, n, steps, items);
+  else
+    scatter_block<V>(blockIdx.x - iblocks, lens, vars, n, start, cursor, ctl, order);
 }
 
 // Count the dwords where two digest buffers differ (autotuner parity gate).
@@ -1115,12 +1133,10 @@ int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, u
                      lanes);
   KB_HIP(hipGetLastError());
   const uint64_t iblocks = (max_items(b.n) + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_items, dim3(static_cast<uint32_t>(iblocks)), dim3(kBlock), 0, s, hist, start,
-                     iend, ctl, b.n, steps, w.items);
-  KB_HIP(hipGetLastError());
   const uint64_t sblocks = (b.n + kScatterTile - 1) / kScatterTile;
-  hipLaunchKernelGGL(k_scatter<V>, dim3(static_cast<uint32_t>(sblocks)), dim3(kBlock), 0, s,
-                     b.lens, b.vars, b.n, start, cursor, ctl, w.order);
+  hipLaunchKernelGGL(k_fill<V>, dim3(static_cast<uint32_t>(iblocks + sblocks)), dim3(kBlock), 0, s,
+                     b.lens, b.vars, b.n, hist, start, cursor, iend, ctl, steps,
+                     static_cast<uint32_t>(iblocks), w.items, w.order);
   KB_HIP(hipGetLastError());
   return KB_OK;
 }
