@@ -99,6 +99,24 @@ def test_uneven_single_variant(kb, o2, v):
     assert _mismatches(got, want)[1] == 0, _mismatches(got, want)
 
 
+def test_count_pass_boundaries(kb, o2):
+    # the count kernel takes whole passes of 8 x 128 messages per wave, then
+    # 64-message chunks with bounds checks: sizes around both boundaries, with
+    # uneven lengths (bucketed order) and with equal lengths (arrival order)
+    rng = np.random.Generator(np.random.PCG64(80))
+    for n in (1, 63, 64, 65, 127, 128, 1023, 1024, 1025, 8191, 8192, 8193, 131072 + 64 + 3):
+        for equal in (False, True):
+            lens = np.full(n, 100) if equal else wl.log_uniform_lengths(rng, n, 3000)
+            var = rng.integers(0, 4, n).astype(np.uint8)
+            b = wl.explicit(lens, seed=81, variant=var, gap=2, lead=1)
+            _say("count boundaries", n, "equal" if equal else "uneven")
+            got = _gpu_mixed(kb, b)
+            want = o2.sha3_batch_mixed(b.variants, b.data, b.offsets, b.lengths)
+            assert _mismatches(got, want)[1] == 0, (n, equal, _mismatches(got, want))
+            got1 = _gpu_batch(kb, 1, b)
+            assert (got1 == o2.sha3_batch(256, b.data, b.offsets, b.lengths)).all(), (n, equal)
+
+
 @pytest.mark.parametrize("case", ["few_long", "many_long"])
 def test_persistent_split_tail(kb, o2, case):
     # the longest messages of a bucketed batch go to the split form (at
