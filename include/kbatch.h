@@ -145,6 +145,23 @@ int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_dat
                     kb_tile* best, double* best_ms, int* rejected, hipStream_t stream);
 
 /*
+ * Keccak-p[b, n_r] (Section 3.1, eqs. 1-10; Table 1 gives the widths): apply
+ * the permutation in place to n states of b bits each.
+ *   b          25, 50, 100, 200, 400, 800 or 1600 (w = b/25 = 2^l)
+ *   n_rounds   1..4096; round i_r runs from 12 + 2l - n_rounds to 12 + 2l - 1
+ *              (FIPS 202's indexing, so b = 1600, n_rounds = 24 is
+ *              Keccak-f[1600]); round constants by i_r mod 255
+ *   d_states   device, n * ceil(b/8) bytes, state s at byte s * ceil(b/8);
+ *              string bit k is bit (k mod 8) of byte k/8, so for b >= 200
+ *              lane (x, y) is the w/8 little-endian bytes at (x + 5y) w/8.
+ *              For b = 25, 50, 100 the unused high bits of each state's last
+ *              byte are cleared.  Any alignment.
+ * One thread per state; asynchronous on `stream`.  Returns KB_EINVAL for a
+ * width not in Table 1, n_rounds out of range or a NULL d_states with n > 0.
+ */
+int keccak_p_batch(int b, int n_rounds, uint8_t* d_states, uint64_t n, hipStream_t stream);
+
+/*
  * Graph capture of a whole batch (all scheduling kernels and the hashing
  * kernel) or a whole tree, for replay with one launch.  The arguments are
  * bound at capture time: replaying hashes whatever the bound buffers hold

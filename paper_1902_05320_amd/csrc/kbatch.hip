@@ -39,6 +39,7 @@
 #include <utility>
 #include <vector>
 
+#include "kb_error.h"
 #include "kbatch.h"
 #include "sponge_device.h"
 #include "split_device.h"
@@ -1361,6 +1362,13 @@ int capture(hipStream_t stream, F&& enqueue, kb_graph* g, kb_graph** out) {
 }
 
 }  // namespace
+
+namespace kb {
+int set_last_error(int code, const char* msg) {
+  g_err = msg ? msg : "";
+  return code;
+}
+}  // namespace kb
 
 extern "C" {
 

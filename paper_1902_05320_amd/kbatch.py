@@ -35,7 +35,7 @@ EXPORTS = (
     "keccak_server_stats", "keccak_server_destroy", "keccak_server_last_error",
     "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
     "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_copy",
-    "keccak_last_error", "keccak_version",
+    "keccak_last_error", "keccak_version", "keccak_p_batch",
 )
 
 
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_batch_mixed.argtypes = [vp, vp, vp, vp, u64, vp, vp]
     lib.keccak_batch_ex.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile), vp]
     lib.keccak_batch_xof.argtypes = [i32, vp, vp, vp, u64, u64, vp, vp]
+    lib.keccak_p_batch.argtypes = [i32, i32, vp, u64, vp]
     lib.merkle_root.argtypes = [i32, vp, u64, u64, vp, vp]
     lib.keccak_digest_bytes.argtypes = [i32]
     lib.keccak_rate_bytes.argtypes = [i32]
@@ -284,6 +285,27 @@ def keccak_batch_xof(security: int, data: torch.Tensor, offsets: torch.Tensor,
     _check(lib.keccak_batch_xof(security, dptr, _ptr(offsets), _ptr(lengths), n, int(out_len),
                                 _ptr(out), _stream_handle(stream)))
     return out
+
+
+KECCAK_P_WIDTHS = (25, 50, 100, 200, 400, 800, 1600)
+
+
+def keccak_p_batch(b: int, n_rounds: int, states: torch.Tensor, stream=None) -> torch.Tensor:
+    """Keccak-p[b, n_rounds] applied in place to every row of `states`
+    (uint8[n, ceil(b/8)] on the device: the packed b-bit strings); returns
+    `states`."""
+    _require_gpu()
+    lib = load_library()
+    if b not in KECCAK_P_WIDTHS:
+        raise ValueError(f"b must be one of {KECCAK_P_WIDTHS}")
+    nbytes = (b + 7) // 8
+    if states.dtype != torch.uint8 or not states.is_cuda or not states.is_contiguous():
+        raise TypeError("states must be a contiguous uint8 device tensor")
+    if states.dim() != 2 or states.shape[1] != nbytes:
+        raise ValueError(f"states must have shape (n, {nbytes})")
+    _check(lib.keccak_p_batch(int(b), int(n_rounds), _ptr(states), states.shape[0],
+                              _stream_handle(stream)))
+    return states
 
 
 def merkle_root(variant, data: torch.Tensor, leaf_size: int, out: torch.Tensor | None = None,

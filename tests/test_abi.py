@@ -66,3 +66,15 @@ def test_argument_errors_need_no_device(lib):
     assert lib.merkle_root(1, p, 100, 0, p, None) == kb.KB_EINVAL
     assert lib.merkle_root(5, p, 100, 10, p, None) == kb.KB_EINVAL
     assert lib.merkle_root(1, p, 100, 10, None, None) == kb.KB_EINVAL
+
+
+def test_keccak_p_argument_errors_need_no_device(lib):
+    from paper_1902_05320_amd import kbatch as kb
+    p = ctypes.c_void_p(0x1000)
+    assert lib.keccak_p_batch(24, 1, p, 1, None) == kb.KB_EINVAL  # not a Table 1 width
+    assert b"b must be" in lib.keccak_last_error()
+    assert lib.keccak_p_batch(1600, 0, p, 1, None) == kb.KB_EINVAL
+    assert lib.keccak_p_batch(1600, 4097, p, 1, None) == kb.KB_EINVAL
+    assert lib.keccak_p_batch(200, 18, None, 3, None) == kb.KB_EINVAL
+    assert lib.keccak_p_batch(25, 12, None, 0, None) == kb.KB_OK  # n == 0: nothing to do
+    assert lib.keccak_last_error() == b""

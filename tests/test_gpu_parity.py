@@ -245,6 +245,41 @@ def test_merkle_deep_trees(kb, o2, v):
         assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], data, leaf)
 
 
+@pytest.mark.parametrize("b", [25, 50, 100, 200, 400, 800, 1600])
+def test_keccak_p_every_width(kb, o2, b):
+    # Keccak-p[b, n_r] in place on packed b-bit states against the bit-level
+    # oracle, for one round, the full 12+2l, a reduced count and more rounds
+    # than 12+2l (negative round indices)
+    import torch
+    from oracle import keccak_ref as ref
+    w, l = ref.width_params(b)
+    nbytes = (b + 7) // 8
+    rng = np.random.Generator(np.random.PCG64(100 + b))
+    n = 257 if b < 1600 else 33
+    states = rng.integers(0, 256, (n, nbytes), dtype=np.uint8)
+    if b % 8:
+        states[:, -1] &= (1 << (b % 8)) - 1
+    for nr in sorted({1, 12 + 2 * l, max(1, 12 + 2 * l - 3), 12 + 2 * l + 7}):
+        _say("keccak_p", b, nr)
+        d = torch.from_numpy(states.copy()).cuda()
+        kb.keccak_p_batch(b, nr, d)
+        got = d.cpu().numpy()
+        for s in range(n):
+            bits = np.unpackbits(states[s], bitorder="little")[:b]
+            want = np.packbits(np.concatenate([ref.keccak_p(bits, b, nr),
+                                               np.zeros(8 * nbytes - b, np.uint8)]),
+                               bitorder="little")
+            assert np.array_equal(got[s], want), (b, nr, s)
+    if b == 1600:
+        _say("keccak_p 1600 x 24 against the lane-level oracle")
+        many = rng.integers(0, 256, (3000, 200), dtype=np.uint8)
+        d = torch.from_numpy(many.copy()).cuda()
+        kb.keccak_p_batch(1600, 24, d)
+        got = d.cpu().numpy()
+        for s in range(0, 3000, 7):
+            assert got[s].tobytes() == o2.keccak_f1600(many[s].tobytes()), s
+
+
 # --------------------------------------------------------------------------
 # Full-size workloads, in the launch configuration the benchmark times
 # --------------------------------------------------------------------------

@@ -406,3 +406,18 @@ def test_merkle_root_bruteforce(o2, d):
     assert o2.merkle_root(d, np.zeros(0, np.uint8), 4) == H(b"")
     a, b = _rand_bytes(1, 4), _rand_bytes(2, 4)
     assert o2.merkle_root(d, np.frombuffer(a + b, np.uint8), 4) == H(H(a) + H(b))
+
+
+@pytest.mark.parametrize("nr", [1, 5, 12, 23])
+def test_reduced_rounds_compose_to_keccak_f(o2, nr):
+    # Keccak-p[1600, n_r] runs rounds 24-n_r .. 23 (reading of the round
+    # indices): after rounds 0 .. 23-n_r it must give Keccak-f[1600], which
+    # hashlib pins through the lane-level oracle.  Indexing the rounds
+    # 0 .. n_r-1 instead fails this for every n_r < 24.
+    rng = np.random.Generator(np.random.PCG64(90 + nr))
+    state = rng.integers(0, 256, 200, dtype=np.uint8).tobytes()
+    A = ref.string_to_state(ref.bytes_to_bits(state), 64)
+    for ir in range(24 - nr):
+        A = ref.rnd(A, ir)
+    got = ref.bits_to_bytes(ref.keccak_p(ref.state_to_string(A), 1600, nr))
+    assert got == o2.keccak_f1600(state)
