@@ -26,6 +26,9 @@
  *     growing it waits for the device.  keccak_reserve() sizes it up front,
  *     keccak_release() frees it.  Calls on one stream are ordered; calls on
  *     different streams use different workspaces and may run concurrently.
+ *     Host threads that share one stream must not call into the library on
+ *     it at the same time (a call may grow the workspace another call on
+ *     that stream is about to use).
  */
 #ifndef KBATCH_H
 #define KBATCH_H
@@ -64,7 +67,7 @@ enum kb_mode {
 
 /* Tuning knobs of the persistent form; a zero field means "library default". */
 typedef struct kb_tile {
-  int32_t block_threads;    /* threads per workgroup: 64, 128 or 256 */
+  int32_t block_threads;    /* 0 or 256: the hashing kernels use 256-thread workgroups */
   int32_t waves_per_simd;   /* persistent grid: resident waves per SIMD (1..8) */
   int32_t steps_per_item;   /* wave-blocks of work per queue item (>= 1) */
   int32_t reserved;

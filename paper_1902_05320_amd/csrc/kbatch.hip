@@ -1226,6 +1226,8 @@ int batch_entry(int variant, const uint8_t* vars, const uint8_t* data, const uin
                 const uint64_t* lens, uint64_t n, uint8_t* out, int mode, const kb_tile* tile,
                 hipStream_t s) {
   g_err.clear();
+  if (tile && tile->block_threads != 0 && tile->block_threads != kBlock)
+    return fail(KB_EINVAL, "tile.block_threads must be 0 or %d", kBlock);
   Batch b{variant, vars, data, offs, lens, n, out, out_stride(variant)};
   int rc = check_batch(b, mode);
   if (rc || n == 0) return rc;

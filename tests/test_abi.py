@@ -62,6 +62,11 @@ def test_argument_errors_need_no_device(lib):
     # unknown mode, bad mixed flag
     assert lib.keccak_batch_ex(1, None, p, p, p, 4, p, 9, None, None) == kb.KB_EINVAL
     assert lib.keccak_batch_ex(-2, None, p, p, p, 4, p, 0, None, None) == kb.KB_EINVAL
+    # a tile asking for another workgroup size
+    t = kb.Tile()
+    t.block_threads = 64
+    assert lib.keccak_batch_ex(1, None, p, p, p, 4, p, 0, ctypes.byref(t), None) == kb.KB_EINVAL
+    assert b"block_threads" in lib.keccak_last_error()
     # tree mode
     assert lib.merkle_root(1, p, 100, 0, p, None) == kb.KB_EINVAL
     assert lib.merkle_root(5, p, 100, 10, p, None) == kb.KB_EINVAL
