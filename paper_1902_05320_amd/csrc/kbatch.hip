@@ -628,15 +628,40 @@ __device__ void make_plan(uint32_t* __restrict__ hist, const uint32_t* __restric
   }
   __syncthreads();
   if (identity) return;
+  // This thread's ranks are the 16 consecutive keys lo .. lo + 15 (64-byte
+  // aligned): fold the copies with 16-byte loads, all issued before use.
+  static_assert(kRanksPerThread == 16, "four 16-byte loads per copy");
+  const uint32_t lo = kKeyBins - kRanksPerThread * (t + 1u);
+  uint4 part[kCopies][4];
+#pragma unroll
+  for (uint32_t k = 0; k < kCopies; ++k) {
+    const uint4* src = reinterpret_cast<const uint4*>((k ? hist_copies + (k - 1) * kKeyBins : hist) + lo);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[k][v] = src[v];
+  }
+  uint32_t byk[kRanksPerThread];  // folded count of key lo + i
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    uint4 a = part[0][v];
+#pragma unroll
+    for (uint32_t k = 1; k < kCopies; ++k) {
+      a.x += part[k][v].x;
+      a.y += part[k][v].y;
+      a.z += part[k][v].z;
+      a.w += part[k][v].w;
+    }
+    byk[4 * v] = a.x;
+    byk[4 * v + 1] = a.y;
+    byk[4 * v + 2] = a.z;
+    byk[4 * v + 3] = a.w;
+    // the folded histogram, read by k_fill and the per-bucket form
+    reinterpret_cast<uint4*>(hist + lo)[v] = a;
+  }
   uint32_t cnt[kRanksPerThread], st[kRanksPerThread], c_sum = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
-    const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
-    uint32_t c = hist[key];
-#pragma unroll
-    for (uint32_t k = 1; k < kCopies; ++k) c += hist_copies[(k - 1) * kKeyBins + key];
-    hist[key] = c;  // the folded histogram, read by k_fill and the per-bucket form
-    cnt[q] = key ? c : 0u;
+    const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);  // = lo + 15 - q
+    cnt[q] = key ? byk[kRanksPerThread - 1u - q] : 0u;
     c_sum += cnt[q];
   }
   uint32_t c_base = block_inclusive_scan(c_sum, scratch) - c_sum;
