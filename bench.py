@@ -377,13 +377,19 @@ def main():
     src_hash = kernel_source_hash()
     traffic = load_traffic(src_hash)
     probe_tops, probe_mhz = kbatch.probe_valu()
+    # the ceiling of the permutation itself on this chip: register-held states,
+    # no memory traffic, as many waves per SIMD as fit
+    perm_gps, perm_waves = kbatch.probe_perm()
+    perm_tops = perm_gps * OPS_PER_PERMUTATION / 1e3
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
                 "traffic": traffic, "kernel": "k_persistent<SHA3-256>",
                 "kernel_ms": round(avg_kernel_s * 1e3, 4), "launches_timed": k_launches,
                 "ops_per_unit": OPS_PER_PERMUTATION, "unit_of_work": "message (1 permutation)",
                 "mix_sol": round(MIX_SOL_TOPS, 2), "frac_of_mix_sol": round(achieved / MIX_SOL_TOPS, 4),
-                "probe_valu_tops": round(probe_tops, 2), "probe_sclk_mhz": round(probe_mhz, 0)}
+                "probe_valu_tops": round(probe_tops, 2), "probe_sclk_mhz": round(probe_mhz, 0),
+                "perm_probe_tops": round(perm_tops, 2), "perm_probe_waves_per_simd": perm_waves,
+                "frac_of_perm_probe": round(achieved / perm_tops, 4)}
 
     result = {
         "metric": METRIC, "value": round(mhash, 2), "unit": "Mhash/s", "n_gpus": 1,

@@ -265,6 +265,18 @@ int keccak_timing_read(double* total_ms, uint64_t* launches);
  * Synchronous; allocates 20 bytes of device memory for its duration. */
 int keccak_probe_valu(uint32_t iters, double* tops, double* sclk_mhz, hipStream_t stream);
 
+/* Probe: throughput of the library's Keccak-f[1600] (Section 3.1) with the
+ * states held in registers and no memory traffic: one state per thread,
+ * `iters` permutations each, on a grid of `waves_per_simd` 256-thread
+ * workgroups per compute unit (0 or more than fit at once: as many as fit).
+ * *gperm_s = permutations per second / 1e9; *waves_used = waves per SIMD
+ * launched.  This is the ceiling a hashing kernel reaches with its loads,
+ * padding and stores fully hidden.  Synchronous; allocates 4 bytes of device
+ * memory for its duration.  KB_EINVAL for null outputs, iters == 0 or a
+ * negative wave count. */
+int keccak_probe_perm(uint32_t iters, int waves_per_simd, double* gperm_s, int* waves_used,
+                      hipStream_t stream);
+
 /* Probe: one device-to-device copy of `bytes` (a multiple of 16, both
  * pointers 16-byte aligned); *gbps = 2 * bytes / time (read + write).
  * Synchronous.  Used to calibrate memory-traffic counters. */

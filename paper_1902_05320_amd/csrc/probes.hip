@@ -1,12 +1,14 @@
 // Measurement probes: the chip's sustained 32-bit VALU issue rate and shader
-// clock, and a device-to-device copy of known size (for scaling memory
-// counters).  They back the roofline figures reported for the hashing
-// kernels; nothing on the hashing path calls them.
+// clock, the throughput of the library's own Keccak-f[1600] on register-held
+// states (no memory traffic), and a device-to-device copy of known size (for
+// scaling memory counters).  They back the roofline figures reported for the
+// hashing kernels; nothing on the hashing path calls them.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "kbatch.h"
+#include "keccak_device.h"
 
 namespace {
 
@@ -44,6 +46,22 @@ __global__ __launch_bounds__(kProbeBlock) void k_valu_probe(uint32_t iters, uint
     clocks[1] = wall_clock64() - w0;
   }
   if (r == 0x9E3779B9u) sink[0] = r;  // keeps the chains live
+}
+
+// Each thread applies the permutation `iters` times to one state held in
+// registers: the hashing kernels' arithmetic with nothing else around it, so
+// its rate is what the permutation's instruction stream itself sustains.
+__global__ __launch_bounds__(kProbeBlock) void k_perm_probe(uint32_t iters,
+                                                            uint32_t* __restrict__ sink) {
+  kb::Lane A[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k)
+    A[k] = kb::Lane{threadIdx.x * 7u + static_cast<uint32_t>(k), blockIdx.x + 3u * k};
+  for (uint32_t it = 0; it < iters; ++it) kb::keccak_f1600(A);
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 25; ++k) r ^= A[k].lo ^ A[k].hi;
+  if (r == 0x9E3779B9u) sink[0] = r;  // keeps the states live
 }
 
 __global__ __launch_bounds__(kProbeBlock) void k_copy_probe(const uint4* __restrict__ src,
@@ -102,6 +120,48 @@ int keccak_probe_valu(uint32_t iters, double* tops, double* sclk_mhz, hipStream_
   if (e1) (void)hipEventDestroy(e1);
   (void)hipFree(sink);
   (void)hipFree(clocks);
+  return rc;
+}
+
+int keccak_probe_perm(uint32_t iters, int waves_per_simd, double* gperm_s, int* waves_used,
+                      hipStream_t stream) {
+  if (!gperm_s || !waves_used || iters == 0 || waves_per_simd < 0) return KB_EINVAL;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return KB_EHIP;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return KB_EHIP;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_perm_probe, kProbeBlock, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    return KB_EHIP;
+  // a 256-thread workgroup puts one wave on each SIMD of its CU
+  const int waves = waves_per_simd == 0 || waves_per_simd > per_cu ? per_cu : waves_per_simd;
+  uint32_t* sink = nullptr;
+  if (hipMalloc(&sink, 4) != hipSuccess) return KB_ENOMEM;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = KB_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = KB_EHIP;
+  const uint32_t grid = static_cast<uint32_t>(cus) * static_cast<uint32_t>(waves);
+  if (rc == KB_OK) {
+    hipLaunchKernelGGL(k_perm_probe, dim3(grid), dim3(kProbeBlock), 0, stream, iters / 4 + 1,
+                       sink);  // warm the clocks up
+    (void)hipEventRecord(e0, stream);
+    hipLaunchKernelGGL(k_perm_probe, dim3(grid), dim3(kProbeBlock), 0, stream, iters, sink);
+    (void)hipEventRecord(e1, stream);
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) rc = KB_EHIP;
+  }
+  if (rc == KB_OK) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess || ms <= 0.f) {
+      rc = KB_EHIP;
+    } else {
+      *gperm_s = static_cast<double>(grid) * kProbeBlock * iters / (ms * 1e-3) / 1e9;
+      *waves_used = waves;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(sink);
   return rc;
 }
 

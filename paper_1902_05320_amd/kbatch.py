@@ -34,8 +34,8 @@ EXPORTS = (
     "keccak_server_create", "keccak_server_submit", "keccak_server_poll", "keccak_server_result",
     "keccak_server_stats", "keccak_server_destroy", "keccak_server_last_error",
     "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
-    "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_copy",
-    "keccak_last_error", "keccak_version", "keccak_p_batch",
+    "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_perm",
+    "keccak_probe_copy", "keccak_last_error", "keccak_version", "keccak_p_batch",
 )
 
 
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.keccak_probe_valu.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), vp]
+    lib.keccak_probe_perm.argtypes = [ctypes.c_uint32, i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int), vp]
     lib.keccak_probe_copy.argtypes = [vp, vp, u64, ctypes.POINTER(ctypes.c_double), vp]
     lib.keccak_autotune.argtypes = [i32, vp, vp, vp, vp, u64, i32, ctypes.POINTER(Tile),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
@@ -124,7 +126,7 @@ def load_library(path: str = LIB_PATH):
               "merkle_root",
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
               "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu",
-              "keccak_probe_copy", "keccak_autotune", "keccak_graph_create",
+              "keccak_probe_perm", "keccak_probe_copy", "keccak_autotune", "keccak_graph_create",
               "keccak_graph_create_merkle", "keccak_graph_launch", "keccak_graph_destroy",
               "keccak_server_create", "keccak_server_submit", "keccak_server_poll",
               "keccak_server_result", "keccak_server_stats", "keccak_server_destroy"):
@@ -519,6 +521,15 @@ def probe_valu(iters: int = 20000, stream=None) -> tuple[float, float]:
     _check(load_library().keccak_probe_valu(int(iters), ctypes.byref(tops), ctypes.byref(mhz),
                                             _stream_handle(stream)))
     return tops.value, mhz.value
+
+
+def probe_perm(iters: int = 400, waves_per_simd: int = 0, stream=None) -> tuple[float, int]:
+    """(G permutations/s of the register-held Keccak-f[1600], waves per SIMD used)."""
+    _require_gpu()
+    g, w = ctypes.c_double(0.0), ctypes.c_int(0)
+    _check(load_library().keccak_probe_perm(int(iters), int(waves_per_simd), ctypes.byref(g),
+                                            ctypes.byref(w), _stream_handle(stream)))
+    return g.value, w.value
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> float:

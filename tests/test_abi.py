@@ -83,3 +83,12 @@ def test_keccak_p_argument_errors_need_no_device(lib):
     assert lib.keccak_p_batch(200, 18, None, 3, None) == kb.KB_EINVAL
     assert lib.keccak_p_batch(25, 12, None, 0, None) == kb.KB_OK  # n == 0: nothing to do
     assert lib.keccak_last_error() == b""
+
+
+def test_probe_argument_errors_need_no_device(lib):
+    from paper_1902_05320_amd import kbatch as kb
+    g, w = ctypes.c_double(0.0), ctypes.c_int(0)
+    assert lib.keccak_probe_perm(0, 0, ctypes.byref(g), ctypes.byref(w), None) == kb.KB_EINVAL
+    assert lib.keccak_probe_perm(10, -1, ctypes.byref(g), ctypes.byref(w), None) == kb.KB_EINVAL
+    assert lib.keccak_probe_perm(10, 0, None, ctypes.byref(w), None) == kb.KB_EINVAL
+    assert lib.keccak_probe_perm(10, 0, ctypes.byref(g), None, None) == kb.KB_EINVAL

@@ -1,6 +1,7 @@
 """GPU: the serving engine (every request's digests equal the same request
-hashed alone, and the oracle), the autotuner's parity gate, and graph
-replays (each replay equals the eager result, with eager work in between)."""
+hashed alone, and the oracle), the autotuner's parity gate, graph replays
+(each replay equals the eager result, with eager work in between), and the
+measurement probes the benchmark reports."""
 
 import numpy as np
 import pytest
@@ -116,3 +117,13 @@ def test_merkle_graph_replays(kb, o2):
         torch.cuda.synchronize()
         assert root.cpu().numpy().tobytes() == want, rep
     g.close()
+
+
+def test_probes_report_rates(kb):
+    _say("probe_perm, probe_valu")
+    g, w = kb.probe_perm(iters=50)
+    assert w >= 1 and 0.1 < g < 1000, (g, w)
+    g1, w1 = kb.probe_perm(iters=50, waves_per_simd=1)
+    assert w1 == 1 and 0.0 < g1 <= 1.5 * g, (g1, g)
+    tops, mhz = kb.probe_valu(iters=2000)
+    assert 1.0 < tops < 200.0 and 100.0 < mhz < 5000.0, (tops, mhz)
