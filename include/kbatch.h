@@ -127,7 +127,9 @@ int keccak_batch_ex(int variant, const uint8_t* d_variants, const uint8_t* d_dat
  * empty leaf).  Leaf digest = H(leaf); a parent = H(left || right) over the
  * two D-byte child digests; an unpaired last node at a level is carried up
  * unchanged.  H is the SHA-3 `variant`.  The D-byte root is written to
- * d_root (device memory).  leaf_size 0 is KB_EINVAL.
+ * d_root (device memory).  leaf_size 0 is KB_EINVAL.  Leaves take a faster
+ * load path when leaf_size, total_len and d_data are all multiples of 8; the
+ * root does not depend on it.
  */
 int merkle_root(int variant, const uint8_t* d_data, uint64_t total_len, uint64_t leaf_size,
                 uint8_t* d_root, hipStream_t stream);

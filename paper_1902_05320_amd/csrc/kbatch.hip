@@ -424,7 +424,13 @@ struct TreeLevels {
 // the lane-split form (five lanes per state, about twice as fast per
 // permutation).  The split form's exchange area reuses the staging rows,
 // which no level uses after the first split one.
-template <int V, int T, bool PF>
+//
+// With W8 every message the kernel hashes is whole 8-byte words at an
+// 8-byte-aligned address (the host checks the leaves; node pairs always are):
+// blocks go from HBM into a per-wave LDS area with the loads that write LDS
+// directly, the next block's while the current one is permuted, and come back
+// as whole words (no byte realignment, no registers holding bytes in flight).
+template <int V, int T, bool PF, bool W8>
 __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, uint64_t total,
                                             uint64_t leaf_size, uint8_t* __restrict__ nodes,
                                             uint8_t* __restrict__ root, int first, int levels,
@@ -437,10 +443,25 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
   // the split path (148), and its leaves are the long chains, so there the
   // in-workgroup levels stay one pair per thread.
   constexpr bool kSplitLevels = !(V == 3 && T == kBlock);
-  __shared__ __align__(16) uint32_t lds[T * S::kRowDw];
-  static_assert(2 * (kGroups * sp::kGroupSlots + 1) <= T * S::kRowDw,
-                "the split exchange area fits in the staging rows");
-  uint32_t* row = lds + threadIdx.x * S::kRowDw;
+  constexpr int kSplitDw = 2 * (kGroups * sp::kGroupSlots + 1);
+  constexpr int kWordsDw = (T / 64) * kb::WordArea<V>::kDw;
+  constexpr int kStageDw = W8 ? kWordsDw : T * S::kRowDw;
+  __shared__ __align__(16) uint32_t lds[kStageDw > kSplitDw ? kStageDw : kSplitDw];
+  static_assert(kSplitDw <= T * S::kRowDw, "the split exchange area fits in the staging rows");
+  uint32_t* row = lds + (W8 ? 0u : threadIdx.x * S::kRowDw);
+  // one message of whole words (W8: through this wave's LDS area) or of any
+  // bytes (staged through this thread's row)
+  auto hash = [&](Lane (&A)[25], const uint8_t* msg, uint64_t len) {
+    if constexpr (W8)
+      kb::sponge_hash_words<V, PF>(
+          A, msg, len,
+          reinterpret_cast<__attribute__((address_space(3))) uint32_t*>(
+              reinterpret_cast<uintptr_t>(lds) & 0xFFFFFFFFu) +
+              (threadIdx.x / 64u) * kb::WordArea<V>::kDw,
+          threadIdx.x & 63u);
+    else
+      kb::sponge_hash<V, PF>(A, msg, len, V, row);
+  };
   const uint64_t w = blockIdx.x;
   auto dst_of = [&](int level, uint64_t j) -> uint8_t* {
     return level == top ? root : nodes + lv.off[level] + j * D;
@@ -451,7 +472,7 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
       const uint64_t off = i * leaf_size;
       const uint64_t len = total - off < leaf_size ? total - off : leaf_size;
       Lane A[25];
-      kb::sponge_hash<V, PF>(A, data + off, len, V, row);
+      hash(A, data + off, len);
       kb::store_digest<V>(dst_of(0, i), A, V);
     }
   }
@@ -466,7 +487,7 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
         uint8_t* dst = dst_of(l + 1, j);
         if (2 * j + 1 < lv.m[l]) {
           Lane A[25];
-          kb::sponge_hash<V, PF>(A, src, 2 * D, V, row);
+          hash(A, src, 2 * D);
           kb::store_digest<V>(dst, A, V);
         } else {
           const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
@@ -1269,9 +1290,12 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
   int L = 0;  // levels above the leaves
   while (lv.m[L] > 1) {
     lv.m[L + 1] = (lv.m[L] + 1) / 2;
-    lv.off[L + 1] = lv.off[L] + lv.m[L] * D;
+    // each level starts 16-byte aligned, so every node pair is 8-byte aligned
+    lv.off[L + 1] = (lv.off[L] + lv.m[L] * D + 15u) & ~uint64_t{15};
     ++L;
   }
+  // leaves of whole 8-byte words at 8-byte-aligned addresses take the W8 kernel
+  const bool w8 = leaf % 8u == 0 && total % 8u == 0 && reinterpret_cast<uintptr_t>(data) % 8u == 0;
   Workspace* w = own;
   int rc = own ? KB_OK : get_ws(s, 0, lv.off[L] + D, &w);
   if (rc) return rc;
@@ -1286,16 +1310,22 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
       const uint64_t blocks = (lv.m[first] + kBlock - 1) / kBlock;
       {
         TimedLaunch tl(s);
-        hipLaunchKernelGGL((k_tree<V, kBlock, kb::kPrefetch<V>>), dim3(static_cast<uint32_t>(blocks)),
-                           dim3(kBlock), 0, s, data, total, leaf, w->tree, root, first, levels, L, lv);
+        if (w8 || first > 0)
+          hipLaunchKernelGGL((k_tree<V, kBlock, kb::kPrefetch<V>, true>),
+                             dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data, total,
+                             leaf, w->tree, root, first, levels, L, lv);
+        else
+          hipLaunchKernelGGL((k_tree<V, kBlock, kb::kPrefetch<V>, false>),
+                             dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data, total,
+                             leaf, w->tree, root, first, levels, L, lv);
       }
       KB_HIP(hipGetLastError());
       first += levels;
     } else {
       {
         TimedLaunch tl(s);
-        hipLaunchKernelGGL((k_tree<V, kTreeTop, false>), dim3(1), dim3(kTreeTop), 0, s, data, total,
-                           leaf, w->tree, root, first, L - first, L, lv);
+        hipLaunchKernelGGL((k_tree<V, kTreeTop, false, true>), dim3(1), dim3(kTreeTop), 0, s, data,
+                           total, leaf, w->tree, root, first, L - first, L, lv);
       }
       KB_HIP(hipGetLastError());
       first = L;

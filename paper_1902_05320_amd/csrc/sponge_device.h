@@ -172,6 +172,111 @@ __device__ __forceinline__ void sponge_hash(Lane (&A)[25], const uint8_t* msg, u
   if (V < kShake128) keccak_round(A, 23);
 }
 
+// The sponge for a message of whole 8-byte words at an 8-byte-aligned
+// address (len % 8 == 0, fixed variant).  Every block then starts 8-byte
+// aligned (R is a multiple of 8), so its bytes can go from HBM straight into
+// LDS with the loads that write LDS directly (no VGPRs hold them in flight)
+// and come back as whole 64-bit words, with no byte realignment.
+//
+// A wave's area (WordArea<V>::kDw dwords, wave-uniform address) holds one
+// block for its 64 lanes, chunk-major: slot c (c < R/16) is 64 lanes x 16
+// bytes, lane l's bytes 16c..16c+15 of its block at byte 16l of the slot;
+// then two slots of 64 lanes x 4 bytes hold an 8-byte half chunk.  A half
+// chunk is the block's last 8 bytes when R % 16 == 8 (SHA3-256/384/512), or
+// the end of a final block that stops 8 bytes into a chunk; a block has at
+// most one (rem % 16 == 8), and nothing is read past the message end.
+template <int V>
+struct WordArea {
+  static constexpr int R = rate_bytes_of(V);
+  static constexpr int kChunks16 = R / 16;
+  static constexpr int kHalfDw = kChunks16 * 256;  // dword offset of the half-chunk slots
+  static constexpr int kDw = kHalfDw + 2 * 64;
+  static_assert(R % 8 == 0, "blocks of whole words");
+};
+
+// Start the loads of `rem` bytes (rem % 8 == 0, rem <= R) at `g` into `area`.
+template <int V>
+__device__ __forceinline__ void words_to_lds(const uint8_t* g, uint32_t rem,
+                                             __attribute__((address_space(3))) uint32_t* area) {
+  using W = WordArea<V>;
+#pragma unroll
+  for (int c = 0; c < W::kChunks16; ++c)
+    if (16u * c + 16u <= rem) __builtin_amdgcn_global_load_lds(g + 16 * c, area + 256 * c, 16, 0, 0);
+  if (rem & 8u) {
+    const uint32_t h = rem & ~15u;
+    __builtin_amdgcn_global_load_lds(g + h, area + W::kHalfDw, 4, 0, 0);
+    __builtin_amdgcn_global_load_lds(g + h + 4, area + W::kHalfDw + 64, 4, 0, 0);
+  }
+}
+
+template <int V, bool PF>
+__device__ __forceinline__ void sponge_hash_words(Lane (&A)[25], const uint8_t* msg, uint64_t len,
+                                                  __attribute__((address_space(3))) uint32_t* area,
+                                                  uint32_t lane) {
+  static_assert(V >= 0 && V <= 3, "SHA3-224/256/384/512 only");
+  using W = WordArea<V>;
+  constexpr int R = W::R;
+  constexpr int RQ = R / 8;  // 64-bit words per block = lanes absorbed
+  const uint64_t nb = len / R + 1u;
+  auto rem_of = [&](uint64_t b) -> uint32_t {
+    return b + 1u == nb ? static_cast<uint32_t>(len - b * static_cast<uint64_t>(R))
+                        : static_cast<uint32_t>(R);
+  };
+  // s_waitcnt fields (gfx9): vmcnt in [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]
+  constexpr int kWaitVm0 = 0x0F70;   // vector memory (these loads included) drained
+  constexpr int kWaitLgkm0 = 0xC07F;  // LDS reads drained
+  if (PF) words_to_lds<V>(msg, rem_of(0), area);
+  // this lane's 16 bytes in chunk slot 0 (dwords; adjacent pairs read as one 64-bit load)
+  const __attribute__((address_space(3))) uint32_t* mine = area + 4u * lane;
+  for (uint64_t b = 0; b < nb; ++b) {
+    const bool fin = b + 1u == nb;
+    const uint32_t rem = rem_of(b);
+    if (!PF) words_to_lds<V>(msg + b * static_cast<uint64_t>(R), rem, area);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    uint2 q[RQ];
+    const uint2 half = make_uint2(area[W::kHalfDw + lane], area[W::kHalfDw + 64 + lane]);
+#pragma unroll
+    for (int j = 0; j < RQ; ++j) {
+      if (j < 2 * W::kChunks16) {
+        const int d = 256 * (j / 2) + 2 * (j % 2);
+        q[j] = make_uint2(mine[d], mine[d + 1]);
+      } else {
+        q[j] = half;
+      }
+    }
+    if (fin) {
+      // past the message: zero; the half chunk of a block ending mid-chunk
+#pragma unroll
+      for (int j = 0; j < RQ; ++j) {
+        if (8u * j >= rem) q[j] = make_uint2(0u, 0u);
+        else if ((rem & 8u) && 8u * j + 8u == rem) q[j] = half;
+      }
+      const uint32_t pw = rem / 8u;
+#pragma unroll
+      for (int j = 0; j < RQ; ++j) q[j].x |= static_cast<uint32_t>(j) == pw ? 0x06u : 0u;
+      q[RQ - 1].y |= 0x80000000u;
+    }
+    if (b == 0) {
+#pragma unroll
+      for (int k = 0; k < 25; ++k)
+        A[k] = k < RQ ? Lane{q[k < RQ ? k : 0].x, q[k < RQ ? k : 0].y} : Lane{0u, 0u};
+    } else {
+#pragma unroll
+      for (int k = 0; k < RQ; ++k) {
+        A[k].lo ^= q[k].x;
+        A[k].hi ^= q[k].y;
+      }
+    }
+    if (PF && !fin) {
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);  // this block's reads done before the area is reused
+      words_to_lds<V>(msg + (b + 1u) * static_cast<uint64_t>(R), rem_of(b + 1u), area);
+    }
+    keccak_rounds_0_22(A);
+    if (!fin) keccak_round(A, 23);
+  }
+  keccak_round(A, 23);
+}
+
 // XOF squeeze (Section 3.2: the output is read r bits at a time, applying
 // the permutation between reads, until out_len bytes are produced).  A holds
 // the state after the last absorbed block's permutation.  Bytes are stored

@@ -213,15 +213,24 @@ def test_order_and_repeat_invariance(kb):
 def test_merkle_small_trees(kb, o2, v):
     import torch
     rng = np.random.Generator(np.random.PCG64(40 + v))
+    # (leaf size, bytes cut from the end when there are several leaves): the
+    # last three keep the leaves and the total whole 8-byte words, the form
+    # whose blocks load straight into registers
     for n_leaves in list(range(1, 18)) + [64, 65, 1000]:
-        for leaf in (1, 13, 4096):
-            total = n_leaves * leaf - (leaf // 3 if n_leaves > 1 else 0)
+        for leaf, cut in ((1, 0), (13, 4), (4096, 1365), (8, 0), (136, 8), (4096, 1360)):
+            total = n_leaves * leaf - (cut if n_leaves > 1 else 0)
             data = rng.integers(0, 256, max(total, 0), dtype=np.uint8)
             _say("merkle", v, n_leaves, leaf, total)
             d = torch.from_numpy(data).cuda() if total else torch.zeros(0, dtype=torch.uint8, device="cuda")
             got = kb.merkle_root(v, d, leaf)
             torch.cuda.synchronize()
             assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], data, leaf)
+    _say("merkle whole words at an odd address")
+    data = rng.integers(0, 256, 64 * 136 + 1, dtype=np.uint8)
+    d = torch.from_numpy(data).cuda()[1:]  # 8-byte multiples, data pointer not 8-byte aligned
+    got = kb.merkle_root(v, d, 136)
+    torch.cuda.synchronize()
+    assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], data[1:], 136)
     _say("merkle empty input")
     d = torch.zeros(0, dtype=torch.uint8, device="cuda")
     got = kb.merkle_root(v, d, 64)
