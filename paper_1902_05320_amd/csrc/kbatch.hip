@@ -455,8 +455,7 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
     if constexpr (W8)
       kb::sponge_hash_words<V, PF>(
           A, msg, len,
-          reinterpret_cast<__attribute__((address_space(3))) uint32_t*>(
-              reinterpret_cast<uintptr_t>(lds) & 0xFFFFFFFFu) +
+          (__attribute__((address_space(3))) uint32_t*)(lds) +
               (threadIdx.x / 64u) * kb::WordArea<V>::kDw,
           threadIdx.x & 63u);
     else
