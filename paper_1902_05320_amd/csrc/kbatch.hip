@@ -456,7 +456,7 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
       kb::sponge_hash_words<V, PF>(
           A, msg, len,
           (__attribute__((address_space(3))) uint32_t*)(lds) +
-              (threadIdx.x / 64u) * kb::WordArea<V>::kDw,
+              __builtin_amdgcn_readfirstlane(threadIdx.x / 64u) * kb::WordArea<V>::kDw,
           threadIdx.x & 63u);
     else
       kb::sponge_hash<V, PF>(A, msg, len, V, row);

@@ -194,11 +194,23 @@ struct WordArea {
   static_assert(R % 8 == 0, "blocks of whole words");
 };
 
-// Start the loads of `rem` bytes (rem % 8 == 0, rem <= R) at `g` into `area`.
+// Start the loads of `rem` bytes (rem % 8 == 0, rem <= R) at `g` into `area`
+// (wave-uniform).  When every active lane loads a whole block the pattern is
+// fixed and issued without per-chunk lane masks.
 template <int V>
 __device__ __forceinline__ void words_to_lds(const uint8_t* g, uint32_t rem,
                                              __attribute__((address_space(3))) uint32_t* area) {
   using W = WordArea<V>;
+  if (__builtin_amdgcn_ballot_w64(rem != static_cast<uint32_t>(W::R)) == 0) {
+#pragma unroll
+    for (int c = 0; c < W::kChunks16; ++c)
+      __builtin_amdgcn_global_load_lds(g + 16 * c, area + 256 * c, 16, 0, 0);
+    if constexpr (W::R % 16 != 0) {
+      __builtin_amdgcn_global_load_lds(g + 16 * W::kChunks16, area + W::kHalfDw, 4, 0, 0);
+      __builtin_amdgcn_global_load_lds(g + 16 * W::kChunks16 + 4, area + W::kHalfDw + 64, 4, 0, 0);
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < W::kChunks16; ++c)
     if (16u * c + 16u <= rem) __builtin_amdgcn_global_load_lds(g + 16 * c, area + 256 * c, 16, 0, 0);
@@ -244,7 +256,9 @@ __device__ __forceinline__ void sponge_hash_words(Lane (&A)[25], const uint8_t* 
         q[j] = half;
       }
     }
-    if (fin) {
+    // (a wave-uniform test first: the selects below would otherwise run on
+    // every block, not only where some lane is at its final one)
+    if (__builtin_amdgcn_ballot_w64(fin) != 0 && fin) {
       // past the message: zero; the half chunk of a block ending mid-chunk
 #pragma unroll
       for (int j = 0; j < RQ; ++j) {
