@@ -53,7 +53,8 @@ using kb::SpongeShape;
 namespace {
 
 constexpr int kBlock = 256;         // threads per workgroup of the hashing kernels
-constexpr int kTreeTop = 1024;      // threads of the workgroup that reduces a tree's last levels
+constexpr int kTreeTop = 1024;      // nodes the workgroup that reduces a tree's last levels takes
+constexpr int kTreeTopThreads = 512;  // its threads: two nodes (one pair) each at its first level
 constexpr uint32_t kKeyBins = 4096;  // block-count buckets
 constexpr int kScatterTile = 4096;  // messages per scatter workgroup
 
@@ -425,12 +426,17 @@ struct TreeLevels {
 // permutation).  The split form's exchange area reuses the staging rows,
 // which no level uses after the first split one.
 //
+// A workgroup owns NODES nodes of level `first`: T for the leaf and middle
+// launches (one leaf or node per thread), 2T for the last workgroup, whose
+// first level is then one pair per thread (a 512-thread workgroup keeps the
+// 256-VGPR limit, where 1024 threads would cap it at 128 and spill).
+//
 // With W8 every message the kernel hashes is whole 8-byte words at an
 // 8-byte-aligned address (the host checks the leaves; node pairs always are):
 // blocks go from HBM into a per-wave LDS area with the loads that write LDS
 // directly, the next block's while the current one is permuted, and come back
 // as whole words (no byte realignment, no registers holding bytes in flight).
-template <int V, int T, bool PF, bool W8>
+template <int V, int T, bool PF, bool W8, int NODES = T>
 __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, uint64_t total,
                                             uint64_t leaf_size, uint8_t* __restrict__ nodes,
                                             uint8_t* __restrict__ root, int first, int levels,
@@ -465,7 +471,8 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
   auto dst_of = [&](int level, uint64_t j) -> uint8_t* {
     return level == top ? root : nodes + lv.off[level] + j * D;
   };
-  if (first == 0) {
+  static_assert(NODES == T || NODES == 2 * T, "one or two nodes per thread");
+  if (NODES == T && first == 0) {  // leaves: only launches with one node per thread take level 0
     const uint64_t i = w * T + threadIdx.x;
     if (i < lv.m[0]) {
       const uint64_t off = i * leaf_size;
@@ -478,7 +485,7 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
   for (int k = 0; k < levels; ++k) {
     const int l = first + k;  // reading level l, writing level l + 1
     __syncthreads();
-    const uint64_t span = static_cast<uint64_t>(T) >> (k + 1);  // pairs of this workgroup
+    const uint64_t span = static_cast<uint64_t>(NODES) >> (k + 1);  // pairs of this workgroup
     if (!kSplitLevels || span > static_cast<uint64_t>(kGroups)) {
       const uint64_t j = w * span + threadIdx.x;
       if (threadIdx.x < span && j < lv.m[l + 1]) {
@@ -1299,8 +1306,8 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
   int rc = own ? KB_OK : get_ws(s, 0, lv.off[L] + D, &w);
   if (rc) return rc;
   // The leaves and the first 8 levels in 256-thread workgroups; more such
-  // launches while over kTreeTop nodes remain; then one kTreeTop-thread
-  // workgroup reduces the rest.  The root is written by whichever launch
+  // launches while over kTreeTop nodes remain; then one workgroup of
+  // kTreeTopThreads threads reduces the rest.  The root is written by whichever launch
   // produces level L (the leaf launch itself for a single leaf).
   int first = 0;
   do {
@@ -1323,8 +1330,9 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
     } else {
       {
         TimedLaunch tl(s);
-        hipLaunchKernelGGL((k_tree<V, kTreeTop, false, true>), dim3(1), dim3(kTreeTop), 0, s, data,
-                           total, leaf, w->tree, root, first, L - first, L, lv);
+        hipLaunchKernelGGL((k_tree<V, kTreeTopThreads, false, true, kTreeTop>), dim3(1),
+                           dim3(kTreeTopThreads), 0, s, data, total, leaf, w->tree, root, first,
+                           L - first, L, lv);
       }
       KB_HIP(hipGetLastError());
       first = L;
