@@ -181,12 +181,11 @@ __global__ __launch_bounds__(kBlock) void k_plain(const uint8_t* __restrict__ da
 // the current block's permutation (for long messages); without, each block
 // is loaded when it is absorbed (fewer registers, for one- and two-block
 // tree nodes).
-template <int V, bool PF = true>
-__device__ __forceinline__ void split_hash(const uint8_t* msg, uint64_t len, int var, uint32_t* o,
-                                           int slot_dw, const kb::split::SplitLane& L) {
+template <int V, bool PF>
+__device__ __forceinline__ void split_absorb(Lane (&a)[5], const uint8_t* msg, uint64_t len,
+                                             int var, const kb::split::SplitLane& L) {
   namespace sp = kb::split;
   using S = SpongeShape<V>;
-  Lane a[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) a[j] = Lane{0u, 0u};
   const int R = rate_of<V>(var);
@@ -203,8 +202,52 @@ __device__ __forceinline__ void split_hash(const uint8_t* msg, uint64_t len, int
     if (PF && !fin) sp::load_words(bw, msg, sh, len, boff + R, R, L);
     sp::split_permute(a, L);
   }
+}
+
+template <int V, bool PF = true>
+__device__ __forceinline__ void split_hash(const uint8_t* msg, uint64_t len, int var, uint32_t* o,
+                                           int slot_dw, const kb::split::SplitLane& L) {
+  Lane a[5];
+  split_absorb<V, PF>(a, msg, len, var, L);
   const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
-  sp::store_words(o, a, dw, slot_dw, L);
+  kb::split::store_words(o, a, dw, slot_dw, L);
+}
+
+// XOF squeeze in the lane-split form (Section 3.2): each lane writes its words
+// that lie in the rate, r bits of output per permutation, until out_len
+// bytes are out; the permutation between reads involves all eight lanes of
+// the group, which all take the same number of turns (out_len is the batch's).
+// Bytes are stored one by one unless out_len is a multiple of 4 and `out` is
+// 4-byte aligned.
+template <int V>
+__device__ __forceinline__ void split_xof(Lane (&a)[5], uint8_t* out, uint64_t out_len,
+                                          const kb::split::SplitLane& L) {
+  constexpr uint32_t R = SpongeShape<V>::kMaxRate;
+  const bool words = (out_len & 3u) == 0 && (reinterpret_cast<uintptr_t>(out) & 3u) == 0;
+  for (uint64_t done = 0;;) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const uint32_t li = L.li[j];
+      if (8u * li < R) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t v = h ? a[j].hi : a[j].lo;
+          const uint64_t at = done + 8u * li + 4u * h;
+          if (at < out_len) {
+            if (words) {
+              *reinterpret_cast<uint32_t*>(out + at) = v;
+            } else {
+              for (uint32_t q = 0; q < 4u && at + q < out_len; ++q)
+                out[at + q] = static_cast<uint8_t>(v >> (8u * q));
+            }
+          }
+        }
+      }
+    }
+    done += R;
+    if (done >= out_len) break;
+    kb::split::split_permute(a, L);
+  }
 }
 
 // Lane-split form: each group of eight lanes hashes one message at a time,
@@ -233,6 +276,12 @@ __global__ __launch_bounds__(kSplitBlock) void k_split(const uint8_t* __restrict
   const int slot_dw = V == kMixed ? 16 : kb::digest_bytes_of(V) / 4;
   for (uint64_t p = static_cast<uint64_t>(blockIdx.x) * kSplitGroups + g; p < count; p += groups) {
     const uint64_t i = order ? order[first + p] : first + p;
+    if constexpr (V >= kShake128) {
+      Lane a[5];
+      split_absorb<V, true>(a, data + offs[i], lens[i], V, L);
+      split_xof<V>(a, out + i * stride, stride, L);
+      continue;
+    }
     const int var = V == kMixed ? vars[i] : V;
     uint32_t* o = reinterpret_cast<uint32_t*>(out + i * stride);
     if (V == kMixed && var > 3) {  // no such variant: the slot is zeroed
@@ -1132,25 +1181,21 @@ int launch_plain(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
 template <int V>
 int launch_split(const Batch& b, const uint32_t* order, uint64_t first, uint64_t count,
                  hipStream_t s) {
-  if constexpr (V >= kShake128) {
-    return fail(KB_EINVAL, "the lane-split form hashes the SHA3 variants only");
-  } else {
-    if (!count) return KB_OK;
-    int dev = 0, cus = 0;
-    KB_HIP(hipGetDevice(&dev));
-    int rc = cu_count(dev, &cus);
-    if (rc) return rc;
-    // one group per message up to 16 waves per CU; beyond that groups loop
-    uint64_t grid = (count + kSplitGroups - 1) / kSplitGroups;
-    if (grid > static_cast<uint64_t>(16 * cus)) grid = 16 * cus;
-    {
-      TimedLaunch tl(s);
-      hipLaunchKernelGGL(k_split<V>, dim3(static_cast<uint32_t>(grid)), dim3(kSplitBlock), 0, s,
-                         b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
-    }
-    KB_HIP(hipGetLastError());
-    return KB_OK;
+  if (!count) return KB_OK;
+  int dev = 0, cus = 0;
+  KB_HIP(hipGetDevice(&dev));
+  int rc = cu_count(dev, &cus);
+  if (rc) return rc;
+  // one group per message up to 16 waves per CU; beyond that groups loop
+  uint64_t grid = (count + kSplitGroups - 1) / kSplitGroups;
+  if (grid > static_cast<uint64_t>(16 * cus)) grid = 16 * cus;
+  {
+    TimedLaunch tl(s);
+    hipLaunchKernelGGL(k_split<V>, dim3(static_cast<uint32_t>(grid)), dim3(kSplitBlock), 0, s,
+                       b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
   }
+  KB_HIP(hipGetLastError());
+  return KB_OK;
 }
 
 template <int V>
@@ -1458,6 +1503,20 @@ int keccak_batch_xof(int security, const uint8_t* d_data, const uint64_t* d_offs
   int rc = check_batch(b, KB_MODE_PERSISTENT);
   if (rc || n == 0) return rc;
   return dispatch(b, KB_MODE_PERSISTENT, nullptr, stream);
+}
+
+int keccak_batch_xof_ex(int security, const uint8_t* d_data, const uint64_t* d_offsets,
+                        const uint64_t* d_lengths, uint64_t n, uint64_t out_len, uint8_t* d_out,
+                        int mode, hipStream_t stream) {
+  g_err.clear();
+  if (security != 128 && security != 256)
+    return fail(KB_EINVAL, "SHAKE security level must be 128 or 256, not %d", security);
+  if (n && out_len == 0) return fail(KB_EINVAL, "out_len must be positive");
+  Batch b{security == 128 ? kShake128 : kShake256, nullptr, d_data, d_offsets, d_lengths, n,
+          d_out, out_len};
+  int rc = check_batch(b, mode);
+  if (rc || n == 0) return rc;
+  return dispatch(b, mode, nullptr, stream);
 }
 
 int keccak_batch_mixed(const uint8_t* d_variants, const uint8_t* d_data,

@@ -28,7 +28,8 @@ KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
 
 # the C ABI entry points, in include/kbatch.h order
 EXPORTS = (
-    "keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_ex", "merkle_root",
+    "keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_xof_ex",
+    "keccak_batch_ex", "merkle_root",
     "keccak_autotune", "keccak_graph_create", "keccak_graph_create_merkle",
     "keccak_graph_launch", "keccak_graph_destroy",
     "keccak_server_create", "keccak_server_submit", "keccak_server_poll", "keccak_server_result",
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_batch_mixed.argtypes = [vp, vp, vp, vp, u64, vp, vp]
     lib.keccak_batch_ex.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile), vp]
     lib.keccak_batch_xof.argtypes = [i32, vp, vp, vp, u64, u64, vp, vp]
+    lib.keccak_batch_xof_ex.argtypes = [i32, vp, vp, vp, u64, u64, vp, i32, vp]
     lib.keccak_p_batch.argtypes = [i32, i32, vp, u64, vp]
     lib.merkle_root.argtypes = [i32, vp, u64, u64, vp, vp]
     lib.keccak_digest_bytes.argtypes = [i32]
@@ -122,7 +124,8 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_last_error.restype = ctypes.c_char_p
     lib.keccak_version.argtypes = []
     lib.keccak_version.restype = ctypes.c_char_p
-    for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_ex",
+    for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_xof_ex",
+              "keccak_batch_ex",
               "merkle_root",
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
               "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu",
@@ -261,12 +264,17 @@ def keccak_batch_mixed(variants: torch.Tensor, data: torch.Tensor, offsets: torc
 
 def keccak_batch_xof(security: int, data: torch.Tensor, offsets: torch.Tensor,
                      lengths: torch.Tensor, out_len: int, out: torch.Tensor | None = None,
-                     stream=None, check_bounds: bool = True) -> torch.Tensor:
-    """SHAKE128/256 of every slice, out_len bytes each; returns uint8[n, out_len]."""
+                     stream=None, check_bounds: bool = True,
+                     mode: str = "persistent") -> torch.Tensor:
+    """SHAKE128/256 of every slice, out_len bytes each; returns uint8[n, out_len].
+
+    mode: "persistent" (default), "plain", "per_bucket" or "split"."""
     _require_gpu()
     lib = load_library()
     if security not in (128, 256):
         raise ValueError("security must be 128 or 256")
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}")
     n = offsets.numel()
     if data.dtype != torch.uint8 or not data.is_cuda:
         raise TypeError("data must be a uint8 device tensor")
@@ -284,8 +292,8 @@ def keccak_batch_xof(security: int, data: torch.Tensor, offsets: torch.Tensor,
     if n == 0:
         return out
     dptr = _ptr(data) if data.numel() else ctypes.c_void_p(out.data_ptr())
-    _check(lib.keccak_batch_xof(security, dptr, _ptr(offsets), _ptr(lengths), n, int(out_len),
-                                _ptr(out), _stream_handle(stream)))
+    _check(lib.keccak_batch_xof_ex(security, dptr, _ptr(offsets), _ptr(lengths), n, int(out_len),
+                                   _ptr(out), MODES[mode], _stream_handle(stream)))
     return out
 
 

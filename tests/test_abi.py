@@ -92,3 +92,13 @@ def test_probe_argument_errors_need_no_device(lib):
     assert lib.keccak_probe_perm(10, -1, ctypes.byref(g), ctypes.byref(w), None) == kb.KB_EINVAL
     assert lib.keccak_probe_perm(10, 0, None, ctypes.byref(w), None) == kb.KB_EINVAL
     assert lib.keccak_probe_perm(10, 0, ctypes.byref(g), None, None) == kb.KB_EINVAL
+
+
+def test_xof_ex_argument_errors_need_no_device(lib):
+    from paper_1902_05320_amd import kbatch as kb
+    p = ctypes.c_void_p(0x1000)
+    assert lib.keccak_batch_xof_ex(192, p, p, p, 1, 32, p, 0, None) == kb.KB_EINVAL
+    assert lib.keccak_batch_xof_ex(128, p, p, p, 1, 0, p, 0, None) == kb.KB_EINVAL
+    assert lib.keccak_batch_xof_ex(128, p, p, p, 1, 32, p, 7, None) == kb.KB_EINVAL
+    assert b"mode" in lib.keccak_last_error()
+    assert lib.keccak_batch_xof_ex(256, None, None, None, 0, 32, None, 3, None) == kb.KB_OK

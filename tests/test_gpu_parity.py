@@ -334,14 +334,17 @@ def test_full_merkle_1gib(kb, o2):
 
 
 @pytest.mark.parametrize("security", [128, 256])
-def test_shake_xof(kb, o2, security):
+@pytest.mark.parametrize("mode", ["persistent", "plain", "split"])
+def test_shake_xof(kb, o2, security, mode):
     import torch
     R = 168 if security == 128 else 136
     b = wl.explicit(list(range(0, 2 * R + 3)) + [5000, 0, 1], seed=60 + security, gap=1, lead=3)
     data, offs, lens, _ = _to_dev(b)
-    for out_len in (1, 3, 32, R - 1, R, R + 1, 3 * R + 5):
-        _say("shake", security, "out_len", out_len)
-        got = kb.keccak_batch_xof(security, data, offs, lens, out_len)
+    # lengths below, at and above one rate, and several squeezes; odd lengths
+    # take the byte-wise stores
+    for out_len in (1, 3, 32, R - 1, R, R + 1, 3 * R + 5, 3 * R + 8):
+        _say("shake", security, mode, "out_len", out_len)
+        got = kb.keccak_batch_xof(security, data, offs, lens, out_len, mode=mode)
         torch.cuda.synchronize()
         got = got.cpu().numpy()
         for i in range(b.n):
