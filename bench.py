@@ -182,8 +182,30 @@ def bench_latency(args, kbatch, workloads, torch, dev):
             row[mode]["same_digests"] = bool(torch.equal(out, ref))
         print(f"[bench] latency {row}", file=sys.stderr, flush=True)
         rows.append(row)
+    # the XOF in the same forms: SHAKE256 (rate 136 bytes, as SHA3-256), 32
+    # output bytes, so the chains are the same length as above
+    xof_rows = []
+    for k, size in cases[:2]:
+        b = workloads.uniform(k, size, seed=7)
+        data = torch.from_numpy(b.data).to(dev)
+        offs = torch.from_numpy(b.offsets).to(dev)
+        lens = torch.from_numpy(b.lengths).to(dev)
+        nb = size // 136 + 1
+        row = {"messages": k, "bytes_each": size, "blocks_each": nb, "out_len": 32}
+        ref = None
+        for mode in ("plain", "persistent", "split"):
+            out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
+            fn = lambda: kbatch.keccak_batch_xof(256, data, offs, lens, 32, out=out, mode=mode,
+                                                 check_bounds=False)
+            t = time_steps(torch, fn, args.steps, args.warmup)
+            row[mode] = {"ms": round(t * 1e3, 4), "us_per_block": round(t * 1e6 / nb, 3)}
+            ref = out.clone() if ref is None else ref
+            row[mode]["same_output"] = bool(torch.equal(out, ref))
+        print(f"[bench] latency shake256 {row}", file=sys.stderr, flush=True)
+        xof_rows.append(row)
     print(json.dumps({"config": {"workload": "latency_few_long_sha3_256", "seed": 6},
-                      "steps": args.steps, "warmup": args.warmup, "cases": rows}), flush=True)
+                      "steps": args.steps, "warmup": args.warmup, "cases": rows,
+                      "shake256": xof_rows}), flush=True)
 
 
 def bench_serving(args, kbatch, workloads, torch, dev):
