@@ -302,7 +302,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the batch would shard across GPUs with no exchange, see DESIGN.md)",
+              "(a batch would shard across GPUs by message, with no exchange between them)",
               file=sys.stderr)
         sys.exit(2)
 
