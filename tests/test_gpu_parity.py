@@ -238,6 +238,23 @@ def test_merkle_small_trees(kb, o2, v):
     assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], np.zeros(0, np.uint8), 64)
 
 
+@pytest.mark.parametrize("v", [0, 3])
+def test_merkle_top_workgroup_boundaries(kb, o2, v):
+    # the leaf launch reduces one level, then the last workgroup takes at most
+    # 1024 nodes: 2047 and 2048 leaves give it 1024 (the first level one pair
+    # per thread), 2049 gives 1025 and a middle launch first, 4096 gives 2048;
+    # leaf sizes 1 (staged loads) and 8 (whole words, LDS-direct loads)
+    import torch
+    rng = np.random.Generator(np.random.PCG64(70 + v))
+    for n_leaves in (2047, 2048, 2049, 4096):
+        for leaf in (1, 8):
+            data = rng.integers(0, 256, n_leaves * leaf, dtype=np.uint8)
+            _say("merkle top", v, n_leaves, leaf)
+            got = kb.merkle_root(v, torch.from_numpy(data).cuda(), leaf)
+            torch.cuda.synchronize()
+            assert got.cpu().numpy().tobytes() == o2.merkle_root(8 * DIGEST[v], data, leaf)
+
+
 @pytest.mark.parametrize("v", [1, 3])
 def test_merkle_deep_trees(kb, o2, v):
     # more than 2^18 leaves: more than 1024 nodes remain after the leaf
