@@ -5,9 +5,11 @@ One step = one keccak_batch call over the whole resident batch (the full
 hot path: block counts, bucketing decision, scheduling and the persistent
 hashing kernel).  W untimed warmup steps, then exactly K timed steps between
 two device synchronisations.  Prints one JSON line with Mhash/s, GB/s hashed,
-the plain one-launch form on the same inputs, the roofline of the dominant
-kernel (timed live with HIP events on its launch stream) and the CPU oracle
-timed on a bounded sample.
+the plain one-launch and one-launch-per-bucket forms on the same inputs (each
+timed after its own warmup, then the persistent and plain forms alternately),
+the roofline of the dominant kernel (timed live with HIP events on its launch
+stream) and the CPU oracle, which hashes the whole batch on the host cores:
+every digest of every form is compared with its output.
 """
 
 from __future__ import annotations
@@ -70,22 +72,50 @@ def load_traffic(src_hash: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(batch, target_s: float = 10.0) -> dict:
-    """The lane-level C oracle, as it stands, on a bounded prefix of the batch."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(batch, extra: bool = True):
+    """The lane-level C oracle, as it stands, on the host cores: the whole
+    batch on every core the process may use (its output is also the expected
+    value of every digest), then a bounded prefix on one core, and Python's
+    hashlib in a single-thread loop as a library reference point.  Returns
+    (report, expected digests)."""
     from oracle import o2
     threads = o2.default_threads()
-    cal = 1 << 14
     t0 = time.perf_counter()
-    o2.sha3_batch(256, batch.data, batch.offsets[:cal], batch.lengths[:cal], threads=threads)
-    rate = cal / max(time.perf_counter() - t0, 1e-6)
-    sample = int(min(batch.n, max(cal, rate * target_s)))
-    t0 = time.perf_counter()
-    o2.sha3_batch(256, batch.data, batch.offsets[:sample], batch.lengths[:sample], threads=threads)
+    want = o2.sha3_batch(256, batch.data, batch.offsets, batch.lengths, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": round(sample / dt / 1e6, 4), "unit": "Mhash/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {sample} of the {batch.n} 64-byte messages (SHA3-256), "
-                      f"lane-level C oracle on {threads} host threads, {dt:.1f} s"}
+    rep = {"value": round(batch.n / dt / 1e6, 4), "unit": "Mhash/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"all {batch.n} 64-byte messages (SHA3-256), lane-level C oracle on "
+                     f"{threads} host threads, {dt:.2f} s",
+           "cpu_model": cpu_model()}
+    if extra:
+        one = 1 << 18
+        t0 = time.perf_counter()
+        o2.sha3_batch(256, batch.data, batch.offsets[:one], batch.lengths[:one], threads=1)
+        d1 = time.perf_counter() - t0
+        rep["single_core"] = {"value": round(one / d1 / 1e6, 4), "unit": "Mhash/s",
+                              "sample": f"first {one} messages, 1 thread, {d1:.2f} s"}
+        k = 1 << 17
+        mv = memoryview(batch.data)
+        t0 = time.perf_counter()
+        for i in range(k):
+            hashlib.sha3_256(mv[i * MSG_BYTES:(i + 1) * MSG_BYTES]).digest()
+        dh = time.perf_counter() - t0
+        rep["hashlib_single_thread"] = {"value": round(k / dh / 1e6, 4), "unit": "Mhash/s",
+                                        "sample": f"first {k} messages, hashlib.sha3_256 loop, "
+                                                  f"{dh:.2f} s"}
+    return rep, want
 
 
 def time_steps(torch, fn, steps, warmup, on_timed=None):
@@ -285,7 +315,9 @@ def main():
     # the GPU's clock ramps over the first dozen or so 2-ms steps of a fresh
     # process (kernel time falls from ~2.0 to ~1.7 ms); warm up past that
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the single-core and hashlib timings (the whole-batch oracle "
+                         "run always happens: it is the bit-exact check)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the library's copy probe over MIB MiB (for counter scaling)")
@@ -361,38 +393,43 @@ def main():
     gbps = N_MSGS * MSG_BYTES * args.steps / wall / 1e9
     print(f"[bench] persistent: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
 
-    # bit-exact spot check of the timed output against the oracle (untimed)
-    from oracle import o2
-    rng = np.random.Generator(np.random.PCG64(7))
-    idx = np.unique(rng.integers(0, N_MSGS, 4096))
-    got = out.cpu().numpy()[idx]
-    want = o2.sha3_batch(256, batch.data, batch.offsets[idx], batch.lengths[idx])
-    bit_exact = bool((got == want).all())
+    out_persistent = out.clone()
 
     plain = per_bucket = None
+    outs = {"persistent": out_persistent}
     if not args.no_plain:
-        for _ in range(args.warmup):
-            step("plain")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step("plain")
-        torch.cuda.synchronize()
-        pw = time.perf_counter() - t0
-        plain = {"mhash_s": round(N_MSGS * args.steps / pw / 1e6, 2),
-                 "ms_per_step": round(1e3 * pw / args.steps, 4)}
-        # the one-launch-per-bucket form (bucketing kernels, the histogram
-        # read back on the host, one plain launch per non-empty bucket)
-        for _ in range(args.warmup):
-            step("per_bucket")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step("per_bucket")
-        torch.cuda.synchronize()
-        bw = time.perf_counter() - t0
-        per_bucket = {"mhash_s": round(N_MSGS * args.steps / bw / 1e6, 2),
-                      "ms_per_step": round(1e3 * bw / args.steps, 4)}
+        for mode in ("plain", "per_bucket"):
+            for _ in range(args.warmup):
+                step(mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                step(mode)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            rec = {"mhash_s": round(N_MSGS * args.steps / w / 1e6, 2),
+                   "ms_per_step": round(1e3 * w / args.steps, 4)}
+            if mode == "plain":
+                plain = rec
+            else:
+                per_bucket = rec
+            outs[mode] = out.clone()
+        # the same two forms again, alternating, so that clock drift over
+        # the run favours neither: median of five rounds of K steps each
+        alt = {"persistent": [], "plain": []}
+        for _ in range(5):
+            for mode in ("plain", "persistent"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    step(mode)
+                torch.cuda.synchronize()
+                alt[mode].append(1e3 * (time.perf_counter() - t0) / args.steps)
+        alternating = {m: round(float(np.median(v)), 4) for m, v in alt.items()}
+        alternating["persistent_over_plain"] = round(alternating["persistent"] / alternating["plain"], 4)
+        print(f"[bench] alternating ms/step: {alternating}", file=sys.stderr, flush=True)
+    else:
+        alternating = None
 
     avg_kernel_s = (k_ms / 1e3) / max(k_launches, 1)
     achieved = N_MSGS * OPS_PER_PERMUTATION / avg_kernel_s / 1e12
@@ -424,15 +461,18 @@ def main():
         "gb_per_s_hashed": round(gbps, 2),
         "plain": plain,
         "per_bucket": per_bucket,
-        "bit_exact_sample": bit_exact,
+        "alternating_ms_per_step": alternating,
         "roofline": roofline,
         "kernel_source_hash": src_hash,
     }
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(batch)
+    # every digest of every form against the oracle (untimed)
+    print("[bench] timing the CPU oracle over the whole batch", file=sys.stderr, flush=True)
+    cpu, want = cpu_baseline(batch, extra=not args.no_cpu_baseline)
+    exact = {m: bool(np.array_equal(o.cpu().numpy(), want)) for m, o in outs.items()}
+    result["bit_exact"] = {"digests_checked": N_MSGS, **exact}
+    result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
-    if not bit_exact:
+    if not all(exact.values()):
         sys.exit(3)
 
 

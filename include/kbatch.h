@@ -250,6 +250,11 @@ int keccak_server_destroy(kb_server* server);
 /* Text of the last server error on the calling host thread. */
 const char* keccak_server_last_error(void);
 
+/* Bytes of device node buffer merkle_root uses for a tree of n_leaves leaves
+ * of the SHA-3 `variant` (every level but the root, each level 16-byte
+ * aligned, plus one digest); 0 for a variant out of range.  Host only. */
+uint64_t keccak_tree_workspace_bytes(int variant, uint64_t n_leaves);
+
 /* Digest and rate sizes in bytes of a variant; -1 if it is out of range. */
 int keccak_digest_bytes(int variant);
 int keccak_rate_bytes(int variant);

@@ -1331,20 +1331,39 @@ int batch_entry(int variant, const uint8_t* vars, const uint8_t* data, const uin
   return dispatch(b, mode, tile, s);
 }
 
+// The levels of a tree over `leaves` leaf digests of D bytes: level l has
+// m[l] = ceil(m[l-1] / 2) nodes stored from byte off[l] of the node buffer
+// (each level starts 16-byte aligned, so every node pair is 8-byte
+// aligned).  Returns L, the number of levels above the leaves.  Level L is
+// the root, which goes to the caller's buffer, so the node buffer needs
+// off[L] bytes; tree_workspace_bytes() adds one digest of slack.
+int tree_levels(uint64_t leaves, uint64_t D, TreeLevels& lv) {
+  lv = TreeLevels{};
+  lv.m[0] = leaves ? leaves : 1;
+  lv.off[0] = 0;
+  int L = 0;
+  while (lv.m[L] > 1) {
+    lv.m[L + 1] = (lv.m[L] + 1) / 2;
+    lv.off[L + 1] = (lv.off[L] + lv.m[L] * D + 15u) & ~uint64_t{15};
+    ++L;
+  }
+  return L;
+}
+
+// Node-buffer bytes of a tree over `leaves` leaves of D-byte digests; it
+// grows with D, so D = 64 sizes a buffer for every variant.
+uint64_t tree_workspace_bytes(uint64_t leaves, uint64_t D) {
+  TreeLevels lv;
+  const int L = tree_levels(leaves, D, lv);
+  return lv.off[L] + D;
+}
+
 template <int V>
 int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* root, hipStream_t s,
                 Workspace* own) {
   constexpr uint64_t D = kb::digest_bytes_of(V);
-  TreeLevels lv{};
-  lv.m[0] = total ? (total + leaf - 1) / leaf : 1;
-  lv.off[0] = 0;
-  int L = 0;  // levels above the leaves
-  while (lv.m[L] > 1) {
-    lv.m[L + 1] = (lv.m[L] + 1) / 2;
-    // each level starts 16-byte aligned, so every node pair is 8-byte aligned
-    lv.off[L + 1] = (lv.off[L] + lv.m[L] * D + 15u) & ~uint64_t{15};
-    ++L;
-  }
+  TreeLevels lv;
+  const int L = tree_levels(total ? (total + leaf - 1) / leaf : 1, D, lv);  // levels above the leaves
   // leaves of whole 8-byte words at 8-byte-aligned addresses take the W8 kernel
   const bool w8 = leaf % 8u == 0 && total % 8u == 0 && reinterpret_cast<uintptr_t>(data) % 8u == 0;
   Workspace* w = own;
@@ -1697,7 +1716,7 @@ int keccak_graph_create_merkle(int variant, const uint8_t* d_data, uint64_t tota
   if (!d_root || (total_len && !d_data)) return fail(KB_EINVAL, "NULL pointer");
   const uint64_t leaves = total_len ? (total_len + leaf_size - 1) / leaf_size : 1;
   kb_graph* g = new kb_graph();
-  const int rc = size_ws(g->ws, 0, (2 * leaves + 1) * 64ull, stream);
+  const int rc = size_ws(g->ws, 0, tree_workspace_bytes(leaves, kb::digest_bytes_of(variant)), stream);
   if (rc) {
     free_ws(g->ws);
     delete g;
@@ -1730,6 +1749,11 @@ int keccak_graph_destroy(kb_graph* graph) {
   return KB_OK;
 }
 
+uint64_t keccak_tree_workspace_bytes(int variant, uint64_t n_leaves) {
+  if (variant < 0 || variant > 3) return 0;
+  return tree_workspace_bytes(n_leaves, kb::digest_bytes_of(variant));
+}
+
 int keccak_digest_bytes(int variant) {
   return variant >= 0 && variant <= 3 ? kb::digest_bytes_of(variant) : -1;
 }
@@ -1741,7 +1765,7 @@ int keccak_rate_bytes(int variant) {
 int keccak_reserve(uint64_t max_msgs, uint64_t max_leaves, hipStream_t stream) {
   g_err.clear();
   Workspace* w = nullptr;
-  const uint64_t tree = max_leaves ? (2 * max_leaves + 1) * 64ull : 0ull;
+  const uint64_t tree = max_leaves ? tree_workspace_bytes(max_leaves, 64) : 0ull;
   return get_ws(stream, max_msgs, tree, &w);
 }
 

@@ -34,8 +34,8 @@ EXPORTS = (
     "keccak_graph_launch", "keccak_graph_destroy",
     "keccak_server_create", "keccak_server_submit", "keccak_server_poll", "keccak_server_result",
     "keccak_server_stats", "keccak_server_destroy", "keccak_server_last_error",
-    "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
-    "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_perm",
+    "keccak_tree_workspace_bytes", "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve",
+    "keccak_release", "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_perm",
     "keccak_probe_copy", "keccak_last_error", "keccak_version", "keccak_p_batch",
 )
 
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_batch_xof_ex.argtypes = [i32, vp, vp, vp, u64, u64, vp, i32, vp]
     lib.keccak_p_batch.argtypes = [i32, i32, vp, u64, vp]
     lib.merkle_root.argtypes = [i32, vp, u64, u64, vp, vp]
+    lib.keccak_tree_workspace_bytes.argtypes = [i32, u64]
+    lib.keccak_tree_workspace_bytes.restype = u64
     lib.keccak_digest_bytes.argtypes = [i32]
     lib.keccak_rate_bytes.argtypes = [i32]
     lib.keccak_reserve.argtypes = [u64, u64, vp]
@@ -500,6 +502,11 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def tree_workspace_bytes(variant, n_leaves: int) -> int:
+    """Device node-buffer bytes merkle_root uses for a tree of n_leaves leaves."""
+    return int(load_library().keccak_tree_workspace_bytes(variant_id(variant), int(n_leaves)))
 
 
 def reserve(max_msgs: int, max_leaves: int = 0, stream=None):

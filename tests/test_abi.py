@@ -102,3 +102,28 @@ def test_xof_ex_argument_errors_need_no_device(lib):
     assert lib.keccak_batch_xof_ex(128, p, p, p, 1, 32, p, 7, None) == kb.KB_EINVAL
     assert b"mode" in lib.keccak_last_error()
     assert lib.keccak_batch_xof_ex(256, None, None, None, 0, 32, None, 3, None) == kb.KB_OK
+
+
+def _tree_bytes_by_level_walk(leaves, D):
+    # every level above the leaves but the root is stored, each level
+    # starting 16-byte aligned; plus one digest
+    m, off = max(leaves, 1), 0
+    while m > 1:
+        off = (off + m * D + 15) // 16 * 16
+        m = (m + 1) // 2
+    return off + D
+
+
+def test_tree_workspace_covers_every_level(lib):
+    # the size a captured tree's private node buffer gets; SHA3-512 needs
+    # more than two digests per leaf when the leaf count is 2^k + 1
+    import numpy as np
+    for v, D in enumerate((28, 32, 48, 64)):
+        for leaves in range(1, 100_001):
+            assert lib.keccak_tree_workspace_bytes(v, leaves) == _tree_bytes_by_level_walk(leaves, D), (v, leaves)
+    for leaves in (2**18 + 1, 2**20 + 1, 3 * 10**6):
+        assert lib.keccak_tree_workspace_bytes(3, leaves) == _tree_bytes_by_level_walk(leaves, 64)
+    # 17 SHA3-512 leaves: levels of 17, 9, 5, 3, 2 nodes (1088, 576, 320, 192,
+    # 128 bytes) and one digest; two digests per leaf plus one (2240) is short
+    assert lib.keccak_tree_workspace_bytes(3, 17) == 2368
+    assert lib.keccak_tree_workspace_bytes(4, 10) == 0

@@ -58,6 +58,43 @@ def test_server_results_equal_alone_and_oracle(kb, o2):
             assert np.array_equal(alone, want), rid
 
 
+def test_server_stream_at_full_request_size_matches_oracle(kb, o2):
+    # requests the size of the serving stream's (1..4096 messages, lengths
+    # log-uniform in [0, 64 KiB], SHA3-256 or SHA3-512), steps of up to 65536
+    # messages, two in flight, submitted in bursts while steps run; every
+    # digest of every request against the oracle
+    import time
+    import torch
+    pool_np, reqs = wl.serving_stream(0.16, 2000.0, 1 << 28, seed=56)
+    assert len(reqs) >= 300
+    pool = torch.from_numpy(pool_np).cuda()
+    _say("server: full-size stream,", len(reqs), "requests,",
+         sum(r.lengths.size for r in reqs), "messages")
+    srv = kb.Server(pool, max_step_msgs=1 << 16, steps_in_flight=2)
+    ids = {}
+    for i, r in enumerate(reqs):
+        ids[srv.submit(r.variant, r.offsets, r.lengths)] = i
+        if i % 40 == 39:
+            time.sleep(0.002)  # the next burst arrives while steps run
+    got = {}
+    while len(got) < len(ids):
+        for rid in srv.poll(wait_ms=200):
+            got[ids[rid]] = srv.result(rid, reqs[ids[rid]].lengths.size)[0]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["rejected"] == 0 and st["steps"] >= 2
+    _say("server: oracle over every request")
+    var = np.concatenate([np.full(r.lengths.size, r.variant, np.uint8) for r in reqs])
+    offs = np.concatenate([r.offsets for r in reqs])
+    lens = np.concatenate([r.lengths for r in reqs])
+    want = o2.sha3_batch_mixed(var, pool_np, offs, lens)
+    at = 0
+    for i, r in enumerate(reqs):
+        k = r.lengths.size
+        assert np.array_equal(got[i], want[at:at + k]), (i, r.variant, k)
+        at += k
+
+
 def test_autotune_candidates_pass_parity(kb, o2):
     import torch
     b = wl.uneven(30000, 6000, seed=52)
@@ -117,6 +154,27 @@ def test_merkle_graph_replays(kb, o2):
         torch.cuda.synchronize()
         assert root.cpu().numpy().tobytes() == want, rep
     g.close()
+
+
+@pytest.mark.parametrize("n_leaves,leaf", [(17, 64), (3000, 100), (2**18 + 1, 8)])
+def test_merkle_graph_sha3_512_odd_leaf_counts(kb, o2, n_leaves, leaf):
+    # a captured tree owns a node buffer sized by the level walk; SHA3-512
+    # at 2^k + 1 and other odd leaf counts needs more than two digests per leaf
+    import torch
+    data_np = wl.merkle(n_leaves * leaf - 3, seed=55)
+    data = torch.from_numpy(data_np).cuda()
+    want = o2.merkle_root(512, data_np, leaf)
+    root = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    _say("merkle graph sha3_512", n_leaves, leaf)
+    g = kb.graph_merkle(3, data, leaf, root)
+    for rep in range(2):
+        root.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert root.cpu().numpy().tobytes() == want, rep
+    g.close()
+    assert kb.merkle_root(3, data, leaf).cpu().numpy().tobytes() == want
 
 
 def test_probes_report_rates(kb):

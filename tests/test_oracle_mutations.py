@@ -104,3 +104,47 @@ def test_sponge_rejects_printed_padding(monkeypatch):
     monkeypatch.setattr(ref, "pad10star1", _pad_as_printed)
     with pytest.raises(AssertionError):
         ref.keccak_c(512, np.zeros(10, dtype=np.uint8), 256)
+
+
+# Keccak-p below 1600 bits: the pins tie each width to the 1600-bit case.
+
+def _keccak_p_indexed_from_24(S, b, nr):
+    # the 1600-bit round indices 24 - n_r .. 23 used at every width
+    w, _ = ref.width_params(b)
+    A = ref.string_to_state(S, w)
+    for ir in range(24 - nr, 24):
+        A = ref.rnd(A, ir)
+    return ref.state_to_string(A)
+
+
+def _rho_offsets_unreduced_left_shift(A):
+    # a slip in the lane rotation: the lane is shifted inside a wider
+    # register and cut back to w bits, so bits that should wrap are lost
+    w = A.shape[2]
+    out = A.copy()
+    for (x, y), s in ref.rho_offsets(64).items():
+        lane = np.concatenate([A[x, y], np.zeros(64, np.uint8)])
+        out[x, y] = np.roll(lane, s)[:w]
+    return out
+
+
+def test_composition_pin_catches_1600_bit_round_indices(monkeypatch):
+    from tests import test_oracle_pins as pins
+    monkeypatch.setattr(ref, "keccak_p", _keccak_p_indexed_from_24)
+    with pytest.raises(AssertionError):
+        pins.test_reduced_rounds_compose_at_every_width(200)
+    pins.test_reduced_rounds_compose_at_every_width(1600)  # identical there
+
+
+def test_truncation_pin_catches_j_below_l(monkeypatch):
+    from tests import test_oracle_pins as pins
+    monkeypatch.setattr(ref, "round_constant", _round_constant_j_below_l)
+    with pytest.raises(AssertionError):
+        pins.test_round_constants_are_the_64_bit_ones_truncated(8)
+
+
+def test_embedding_pin_catches_a_rho_slip_below_64_bits(monkeypatch):
+    from tests import test_oracle_pins as pins
+    monkeypatch.setattr(ref, "rho", _rho_offsets_unreduced_left_shift)
+    with pytest.raises(AssertionError):
+        pins.test_round_without_iota_embeds_in_the_1600_bit_round(200)

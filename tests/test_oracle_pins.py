@@ -421,3 +421,74 @@ def test_reduced_rounds_compose_to_keccak_f(o2, nr):
         A = ref.rnd(A, ir)
     got = ref.bits_to_bytes(ref.keccak_p(ref.state_to_string(A), 1600, nr))
     assert got == o2.keccak_f1600(state)
+
+
+# --------------------------------------------------------------------------
+# Keccak-p below 1600 bits (Table 1).  The paper prints no value for these
+# widths and no independent implementation of them is at hand, so each
+# width-dependent part is tied to the 1600-bit permutation, which hashlib
+# pins: the round without iota by periodic embedding, iota by truncation of
+# the 64-bit round constants, and the round-index reading by composition.
+# --------------------------------------------------------------------------
+
+SMALL_WIDTHS = [25, 50, 100, 200, 400, 800]
+
+
+def _round_without_iota(A):
+    return ref.chi(ref.pi(ref.rho(ref.theta(A))))
+
+
+@pytest.mark.parametrize("b", SMALL_WIDTHS)
+def test_round_without_iota_embeds_in_the_1600_bit_round(b):
+    # A state whose 64-bit lanes each repeat a w-bit pattern 64/w times stays
+    # so under theta, rho, pi and chi (rho's offsets act mod w, theta's
+    # z - 1 wraps mod w), and the pattern then follows the width-w round.
+    w, _ = ref.width_params(b)
+    rng = np.random.Generator(np.random.PCG64(200 + b))
+    for _ in range(4):
+        a = rng.integers(0, 2, size=(5, 5, w), dtype=np.uint8)
+        A = np.tile(a, (1, 1, 64 // w))
+        assert np.array_equal(_round_without_iota(A), np.tile(_round_without_iota(a), (1, 1, 64 // w)))
+
+
+@pytest.mark.parametrize("w", [1, 2, 4, 8, 16, 32])
+def test_round_constants_are_the_64_bit_ones_truncated(w):
+    # eq. 8 sets bits 2^j - 1 for j = 0..l; with l = log2 w those are exactly
+    # the positions below w of the seven 64-bit ones, so RC_w = RC_64 mod 2^w
+    # (a "j < l" reading drops bit 2^l - 1 and fails)
+    for ir in range(0, 300):
+        assert np.array_equal(ref.round_constant(ir, w), ref.round_constant(ir, 64)[:w]), (w, ir)
+
+
+@pytest.mark.parametrize("b", SMALL_WIDTHS)
+def test_theta_of_one_bit_hits_two_columns(b):
+    # closed form: a single bit at (x, y, z) sets column parity C[x, z], so
+    # theta adds D to columns (x+1, z) and (x-1, z+1): eleven bits in all
+    w, _ = ref.width_params(b)
+    rng = np.random.Generator(np.random.PCG64(300 + b))
+    for _ in range(6):
+        x, y, z = (int(v) for v in (rng.integers(0, 5), rng.integers(0, 5), rng.integers(0, w)))
+        A = np.zeros((5, 5, w), dtype=np.uint8)
+        A[x, y, z] = 1
+        want = A.copy()
+        want[(x + 1) % 5, :, z] ^= 1
+        want[(x - 1) % 5, :, (z + 1) % w] ^= 1
+        assert np.array_equal(ref.theta(A), want), (b, x, y, z)
+        assert int(ref.theta(A).sum()) == 11
+
+
+@pytest.mark.parametrize("b", SMALL_WIDTHS + [1600])
+def test_reduced_rounds_compose_at_every_width(b):
+    # Keccak-p[b, n] after rounds 0 .. 12+2l-n-1 equals Keccak-p[b, 12+2l]:
+    # the round indices of n reduced rounds end at 12+2l-1 for every width
+    # (indexing them 24-n .. 23 at every width fails this below b = 1600)
+    w, l = ref.width_params(b)
+    full = 12 + 2 * l
+    rng = np.random.Generator(np.random.PCG64(400 + b))
+    S = rng.integers(0, 2, size=b, dtype=np.uint8)
+    want = ref.keccak_p(S, b, full)
+    for n in sorted({1, 2, full // 2, full - 1}):
+        A = ref.string_to_state(S, w)
+        for ir in range(full - n):
+            A = ref.rnd(A, ir)
+        assert np.array_equal(ref.keccak_p(ref.state_to_string(A), b, n), want), (b, n)
