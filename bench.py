@@ -47,7 +47,7 @@ PEAK_INT32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 MIX_SOL_TOPS = PEAK_INT32_TOPS * OPS_PER_PERMUTATION / (
     OPS_PER_PERMUTATION + HALF_RATE_OPS_PER_PERMUTATION)
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_persistent_sha3_256_2p24x64.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_first_sha3_256_2p24x64.json")
 
 
 def kernel_source_hash() -> str:
@@ -386,7 +386,9 @@ def main():
         step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    k_ms, k_launches = kbatch.timing_read()
+    # the dominant kernel: the first pass hashes every chunk of this batch
+    k_ms, k_launches = kbatch.timing_read("first_pass")
+    k2_ms, k2_launches = kbatch.timing_read("second_pass")
     kbatch.timing_enable(False)
     ms_per_step = 1e3 * wall / args.steps
     mhash = N_MSGS * args.steps / wall / 1e6
@@ -442,8 +444,9 @@ def main():
     perm_tops = perm_gps * OPS_PER_PERMUTATION / 1e3
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
                 "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4),
-                "traffic": traffic, "kernel": "k_persistent<SHA3-256>",
+                "traffic": traffic, "kernel": "k_first<SHA3-256>",
                 "kernel_ms": round(avg_kernel_s * 1e3, 4), "launches_timed": k_launches,
+                "second_pass_ms": round(k2_ms / max(k2_launches, 1), 4),
                 "ops_per_unit": OPS_PER_PERMUTATION, "unit_of_work": "message (1 permutation)",
                 "mix_sol": round(MIX_SOL_TOPS, 2), "frac_of_mix_sol": round(achieved / MIX_SOL_TOPS, 4),
                 "probe_valu_tops": round(probe_tops, 2), "probe_sclk_mhz": round(probe_mhz, 0),

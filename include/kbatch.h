@@ -54,7 +54,9 @@ enum kb_status {
 
 /* Scheduling forms of a batch (all give identical digests). */
 enum kb_mode {
-  KB_MODE_PERSISTENT = 0, /* bucket by block count, longest first, one persistent launch */
+  KB_MODE_PERSISTENT = 0, /* two resident-grid launches: arrival order, hashing every
+                             64-message chunk of one-block messages at once; the other
+                             messages bucketed by block count and hashed longest first */
   KB_MODE_PLAIN = 1,      /* one thread per message in arrival order, one launch (the
                              paper's "one thread per message", Section 4.1) */
   KB_MODE_PER_BUCKET = 2, /* bucket by block count, one plain launch per bucket (waits on
@@ -86,6 +88,24 @@ typedef struct kb_tile {
  */
 int keccak_batch(int variant, const uint8_t* d_data, const uint64_t* d_offsets,
                  const uint64_t* d_lengths, uint64_t n, uint8_t* d_digests, hipStream_t stream);
+
+/*
+ * keccak_batch_noalloc -- keccak_batch that allocates nothing, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The scheduling workspace
+ * is one static array on each device (about 4.6 MiB, for up to
+ * KB_NOALLOC_MAX_MSGS messages), present from the library's load until the
+ * process ends; the first call on a device looks it up and clears it on
+ * `stream`, and each call leaves it cleared for the next.  Every call on a
+ * device shares that one array: calls that overlap on one device (on
+ * different streams, or from host threads at once) race on it and give
+ * wrong digests, so serialise them.  Same arguments, output and persistent
+ * form as keccak_batch; KB_EINVAL for n > KB_NOALLOC_MAX_MSGS.
+ */
+#define KB_NOALLOC_MAX_MSGS (1u << 20)
+int keccak_batch_noalloc(int variant, const uint8_t* d_data, const uint64_t* d_offsets,
+                         const uint64_t* d_lengths, uint64_t n, uint8_t* d_digests,
+                         hipStream_t stream);
 
 /*
  * keccak_batch_mixed -- like keccak_batch with a variant per message.
@@ -194,6 +214,19 @@ int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d
                         const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n,
                         uint8_t* d_digests, int mode, const kb_tile* tile, hipStream_t stream,
                         kb_graph** out);
+/*
+ * keccak_graph_create_counted -- capture the persistent form over a batch
+ * whose message count is read from device memory each time the graph runs:
+ * d_count (uint32, device) then holds n, taken as max_n if larger.  The
+ * descriptor arrays and d_digests are sized for max_n messages.  For loops
+ * with fixed-capacity buffers (a serving step fills the descriptors and the
+ * count, then replays the graph).  max_n in [1, 2^32 - 1); other arguments
+ * as keccak_graph_create (variant -1 = mixed).
+ */
+int keccak_graph_create_counted(int variant, const uint8_t* d_variants, const uint8_t* d_data,
+                                const uint64_t* d_offsets, const uint64_t* d_lengths,
+                                const uint32_t* d_count, uint64_t max_n, uint8_t* d_digests,
+                                hipStream_t stream, kb_graph** out);
 int keccak_graph_create_merkle(int variant, const uint8_t* d_data, uint64_t total_len,
                                uint64_t leaf_size, uint8_t* d_root, hipStream_t stream,
                                kb_graph** out);
@@ -205,12 +238,19 @@ int keccak_graph_destroy(kb_graph* graph);
  * pool (batch mode of Section 4 applied to a stream of requests).  A request
  * is a variant and n slices (offset, length) of the pool, given as host
  * arrays (copied at submit).  A worker thread admits queued requests in
- * arrival order into steps of at most max_step_msgs messages, keeps up to
- * steps_in_flight steps on the GPU at once (one HIP stream and one set of
- * device buffers each, allocated at create), and hashes each step with
- * keccak_batch_mixed.  A request larger than a step is rejected (KB_ENOMEM).
- * Results are 64-byte digest slots, one per message, zero past the digest.
- * Thread-safe: any thread may submit and poll.
+ * arrival order into steps while a step has room: at most max_step_msgs
+ * message slots (the step's device buffers) and, if max_step_bytes is set,
+ * at most that many message bytes (the step's work).  A request never
+ * straddles steps; one larger than a step is rejected (KB_ENOMEM).  Up to
+ * steps_in_flight steps run on the GPU at once, each with its own HIP
+ * stream, pinned host buffers and device buffers (allocated at create), so
+ * requests that arrive while steps run are admitted as soon as a step slot
+ * frees up and their work overlaps the running steps.  Each step is one
+ * replay of a HIP graph captured at create: the descriptor and count
+ * uploads, both passes of the mixed-variant persistent form reading the
+ * count from device memory, and the digest download (copy sizes set per
+ * step).  Results are 64-byte digest slots, one per message, zero past the
+ * digest.  Thread-safe: any thread may submit and poll.
  *
  * executor (optional): if set, the server never touches the GPU and instead
  * calls executor(user, variants, offsets, lengths, n, digests) on the worker
@@ -219,14 +259,16 @@ int keccak_graph_destroy(kb_graph* graph);
  */
 typedef int (*kb_step_executor)(void* user, const uint8_t* h_variants, const uint64_t* h_offsets,
                                 const uint64_t* h_lengths, uint64_t n, uint8_t* h_digests);
+enum { KB_SERVER_EAGER = 1 /* flags: steps as separate copies and launches, no graph */ };
 typedef struct kb_server_config {
   const uint8_t* d_pool;   /* device byte pool the requests slice */
   uint64_t pool_bytes;     /* its size: every slice must lie inside */
   uint64_t max_step_msgs;  /* message slots per step */
   int32_t steps_in_flight; /* 1..8 */
-  int32_t reserved;
+  uint32_t flags;          /* KB_SERVER_EAGER or 0 */
   kb_step_executor executor;
   void* executor_user;
+  uint64_t max_step_bytes; /* message bytes per step; 0 = no limit */
 } kb_server_config;
 typedef struct kb_server_stats {
   uint64_t steps, messages, bytes, completed, rejected, pending, max_step_msgs_seen;
@@ -267,14 +309,28 @@ int keccak_reserve(uint64_t max_msgs, uint64_t max_leaves, hipStream_t stream);
 int keccak_release(void);
 
 /* Measurement hook.  While enabled (on != 0) every hashing-kernel launch
- * (persistent, plain, per-bucket and tree-level kernels) is bracketed by a
- * pair of HIP events recorded on the stream it is launched on.  Enabling
- * clears the record.  Not for use during graph capture. */
+ * (both passes of the persistent form, the plain, split and tree kernels)
+ * is bracketed by a pair of HIP events recorded on the stream it is launched
+ * on.  Enabling clears the record.  Launches recorded into a graph are not
+ * bracketed. */
 int keccak_timing_enable(int on);
 
 /* Sum of the bracketed kernel durations in milliseconds and the number of
  * bracketed launches since timing was enabled; waits for those events. */
 int keccak_timing_read(double* total_ms, uint64_t* launches);
+
+/* Kinds of bracketed kernels. */
+enum kb_kernel {
+  KB_KERNEL_FIRST_PASS = 0,  /* persistent form: the arrival-order pass */
+  KB_KERNEL_SECOND_PASS = 1, /* persistent form: the bucketed pass */
+  KB_KERNEL_PLAIN = 2,       /* one thread per message (plain and per-bucket forms) */
+  KB_KERNEL_SPLIT = 3,       /* lane-split form */
+  KB_KERNEL_TREE = 4         /* tree mode */
+};
+
+/* keccak_timing_read restricted to the kernels of one kind; KB_EINVAL for
+ * an unknown kind. */
+int keccak_timing_read_kernel(int kind, double* total_ms, uint64_t* launches);
 
 /* Probe: sustained 32-bit VALU issue rate of the current device (tera
  * lane-operations per second; a grid of 8 waves per SIMD running `iters`

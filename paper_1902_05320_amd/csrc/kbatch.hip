@@ -39,7 +39,7 @@
 #include <utility>
 #include <vector>
 
-#include "kb_error.h"
+#include "kb_internal.h"
 #include "kbatch.h"
 #include "sponge_device.h"
 #include "split_device.h"
@@ -55,20 +55,32 @@ namespace {
 constexpr int kBlock = 256;         // threads per workgroup of the hashing kernels
 constexpr int kTreeTop = 1024;      // nodes the workgroup that reduces a tree's last levels takes
 constexpr int kTreeTopThreads = 512;  // its threads: two nodes (one pair) each at its first level
-constexpr uint32_t kKeyBins = 4096;  // block-count buckets
-constexpr int kScatterTile = 4096;  // messages per scatter workgroup
+constexpr uint32_t kKeyBins = 4096;  // block-count buckets (4095 = "4095 or more")
+constexpr uint32_t kLdsBins = 2048;  // the first pass counts keys below this in LDS
+constexpr uint32_t kScatterChunks = 64;  // deferred 64-message chunks per scatter tile
+constexpr uint32_t kLine = 64;       // 32-bit words per 256-byte line
 
-// control words (uint32 indices into the ctl area)
+// Control words (uint32 indices into the ctl area), written by the plan.
 enum : int {
-  CTL_NITEMS = 2,    // number of queue items
-  CTL_IDENTITY = 3,  // 1: arrival order kept, order[] unused
-  CTL_MAXKEY = 4,    // largest block-count key seen
-  CTL_ID_PER = 5,    // arrival order: messages per queue item
-  CTL_USEFUL = 6,    // uint64 (words 6, 7): sum of (clamped) block counts
-  CTL_IDLE = 8,      // uint64 (words 8, 9): lane-slots arrival-order waves would idle
-  CTL_PRIO_KEY = 10, // front waves raise their priority on items of at least this many blocks
-  CTL_SPLIT_N = 11,  // bucketed order positions [0, CTL_SPLIT_N) are hashed in the split form
+  CTL_NITEMS = 0,       // queue items of the second pass
+  CTL_TILES = 1,        // its tiles: item tiles, then scatter tiles
+  CTL_ITEM_TILES = 2,
+  CTL_NDEF_CHUNKS = 3,  // chunks the first pass deferred
+  CTL_MAXKEY = 4,       // largest block-count key deferred
+  CTL_PRIO_KEY = 5,     // front waves raise their priority on items of at least this many blocks
+  CTL_SPLIT_N = 6,      // bucketed order positions [0, CTL_SPLIT_N) are hashed in the split form
+  CTL_SPIN_LIMIT = 7,   // set if a second-pass workgroup gave up waiting for the tiles
+  CTL_USEFUL = 8,       // uint64 (words 8, 9): block counts of the deferred messages
   CTL_WORDS = 64
+};
+
+// Counters of the two passes, one 256-byte line each.
+enum : uint32_t {
+  SY_TICKET = 0,  // first-pass workgroups finished (the last one makes the plan)
+  SY_DEFER = 1,   // entries of the deferred-chunk list
+  SY_CLAIM = 2,   // second-pass tiles claimed
+  SY_DONE = 3,    // second-pass tiles finished
+  kSyncCounters = 4
 };
 
 // One flag per SIMD of the chip, indexed from the wave's hardware id
@@ -79,29 +91,67 @@ constexpr uint32_t kSimdSlots = 8 * 8 * 2 * 16 * 4;
 // The queue is dealt round-robin into kQueues sub-queues (item t goes to
 // sub-queue t mod kQueues, so each keeps the longest-first order); a wave
 // starts on the sub-queue of its XCD.  Each sub-queue is one uint64 counter
-// (items taken from the front | taken from the back << 32) on its own
-// 256-byte line.
+// (items taken from the front | taken from the back << 32) on its own line.
 constexpr uint32_t kQueues = 8;
-constexpr uint32_t kQueueStrideDw = 64;
 // the sub-queues, then the counter of split items on a line of its own
-constexpr uint32_t kQueueAreaDw = (kQueues + 1) * kQueueStrideDw;
+constexpr uint32_t kQueueAreaDw = (kQueues + 1) * kLine;
 
-// k_count accumulates into kCopies partial histograms and control sums (copy
-// = workgroup index mod 8, which is its XCD), so that the workgroups' closing
-// atomics spread over eight addresses instead of one; k_plan folds them.
+// The first pass accumulates into kCopies partial histograms and partial
+// sums (copy = workgroup index mod 8, which is its XCD), so that the
+// workgroups' closing atomics spread over eight addresses; the plan folds
+// them and clears the copies it found dirty.
 constexpr uint32_t kCopies = 8;
-constexpr uint32_t kPartialWords = 8;  // per copy: useful (u64), idle (u64), max key
-enum : uint32_t { P_USEFUL = 0, P_IDLE = 2, P_MAXKEY = 4 };
-// Workspace metadata layout (uint32 words): hist | start | cursor | iend |
-// ctl | queues | SIMD flags | hist copies 1..7 | partials.
-constexpr uint32_t kHistCopiesOff = 4 * kKeyBins + CTL_WORDS + kQueueAreaDw + kSimdSlots;
-constexpr uint32_t kPartialsOff = kHistCopiesOff + (kCopies - 1) * kKeyBins;
+enum : uint32_t { P_USEFUL = 0, P_MAXKEY = 2, P_DIRTY = 3 };  // per copy, on its own line
+
+// Workspace metadata layout (uint32 words).  Every counter and partial sum
+// is zero between calls: the workspace is cleared when it is allocated, and
+// each call's plan clears what the call used.
+enum : uint32_t {
+  M_HIST = 0,                                   // kCopies x kKeyBins partial histograms
+  M_FOLD = M_HIST + kCopies * kKeyBins,         // deferred messages per key
+  M_START = M_FOLD + kKeyBins,                  // first bucketed position of each key
+  M_CURSOR = M_START + kKeyBins,                // scatter cursors
+  M_IEND = M_CURSOR + kKeyBins,                 // inclusive prefix of queue items by rank
+  M_CTL = M_IEND + kKeyBins,
+  M_QUEUES = M_CTL + CTL_WORDS,
+  M_SYNC = M_QUEUES + kQueueAreaDw,
+  M_PARTIALS = M_SYNC + kSyncCounters * kLine,
+  M_SIMD = M_PARTIALS + kCopies * kLine,
+  kMetaWords = M_SIMD + kSimdSlots
+};
 
 struct WorkItem {
-  uint32_t begin, end;  // positions in order[] (message indices in arrival order)
-  uint32_t key;         // block-count bucket of the item (0 in arrival order)
+  uint32_t begin, end;  // positions in order[]
+  uint32_t key;         // block-count bucket of the item
   uint32_t pad;
 };
+
+// Arguments of the two passes of the persistent form (by value).
+struct PassArgs {
+  const uint8_t* data;
+  const uint64_t* offs;
+  const uint64_t* lens;
+  const uint8_t* vars;
+  uint64_t n;
+  uint8_t* out;
+  uint64_t stride;      // output bytes per message
+  uint32_t* meta;       // kMetaWords words, layout above
+  uint32_t* deferred;   // deferred chunk indices, ceil(n / 64) entries
+  uint32_t* order;      // bucketed order of the deferred messages, n entries
+  WorkItem* items;      // queue items, max_items(n) entries
+  uint32_t steps;       // permutations per lane in one queue item
+  uint32_t split_cap;   // most messages the split tail may take (mixed kernel)
+  uint64_t lanes;       // resident lanes of the second pass
+  int hash;             // 0: count and scatter only (the per-bucket form)
+  const uint32_t* n_dev;  // if set: the message count, read on the device (at most n)
+};
+
+// The message count a pass works on: n, or the device word when given.
+__device__ __forceinline__ uint64_t pass_count(const PassArgs& a) {
+  if (!a.n_dev) return a.n;
+  const uint64_t c = *a.n_dev;
+  return c < a.n ? c : a.n;
+}
 
 template <int V>
 __device__ __forceinline__ int rate_of(int var) {
@@ -295,9 +345,6 @@ __global__ __launch_bounds__(kSplitBlock) void k_split(const uint8_t* __restrict
   }
 }
 
-// Persistent form: waves pop queue items until the queue is drained.  Every
-// wave leaves the loop once the counter passes the item count, so the grid
-// always drains.
 // Index of the SIMD this wave runs on, from the HW_ID register (SIMD [5:4],
 // CU [11:8], SH [12], SE [15:13]) and XCC_ID [3:0].  Used only to spread the
 // front-of-queue waves one per SIMD; a wrong index costs balance, never
@@ -308,148 +355,6 @@ __device__ __forceinline__ uint32_t simd_slot() {
   const uint32_t simd = (hw >> 4) & 3u, cu = (hw >> 8) & 15u, sh = (hw >> 12) & 1u,
                  se = (hw >> 13) & 7u;
   return ((((xcc * 8u + se) * 2u + sh) * 16u + cu) * 4u) + simd;
-}
-
-// Persistent form.  Queue items are ordered longest first.  On each SIMD one
-// wave (the first to claim the SIMD's flag) takes items from the front at
-// raised issue priority while they are long, so the long absorb chains that
-// bound the makespan run back to back at full rate; the other resident waves
-// take the shortest items from the back and fill the issue slots the front
-// wave leaves idle.  Both ends of a sub-queue advance one packed 64-bit
-// counter, so no item is taken twice.  A wave drains the sub-queue of its own
-// XCD first and then the others in turn, so every item is taken whatever the
-// mapping of waves to XCDs, and every wave leaves once all sub-queues are
-// empty, so the grid always drains.  In arrival order (uniform work) every
-// wave takes from the front at normal priority.
-template <int V>
-__global__ __launch_bounds__(kBlock) void k_persistent(
-    const uint8_t* __restrict__ data, const uint64_t* __restrict__ offs,
-    const uint64_t* __restrict__ lens, const uint8_t* __restrict__ vars,
-    const uint32_t* __restrict__ order, const WorkItem* __restrict__ items,
-    const uint32_t* __restrict__ ctl, unsigned long long* __restrict__ queues,
-    uint32_t* __restrict__ simd_flags, uint8_t* __restrict__ out, uint64_t stride) {
-  using S = SpongeShape<V>;
-  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
-  static_assert(2 * (kSplitGroups * kb::split::kGroupSlots + 1) <= 64 * S::kRowDw,
-                "a wave's staging rows hold its split exchange area");
-  uint32_t* row = lds + threadIdx.x * S::kRowDw;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t n_items = ctl[CTL_NITEMS];
-  const bool sorted = ctl[CTL_IDENTITY] == 0u;
-  const uint32_t prio_key = ctl[CTL_PRIO_KEY];
-  const uint32_t* ord = sorted ? order : nullptr;
-  uint32_t claim = 0;
-  if (sorted && lane == 0) claim = atomicCAS(&simd_flags[simd_slot()], 0u, 1u) == 0u ? 1u : 0u;
-  const bool front = !sorted || __builtin_amdgcn_readfirstlane(__shfl(claim, 0)) != 0u;
-  const unsigned long long step = 1ull << (front ? 0 : 32);
-  const uint32_t home = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kQueues - 1u);
-  // Split items first: the front waves hash the longest messages (bucketed
-  // positions [0, split_n)) eight at a time, one per 8-lane group, in the
-  // lane-split form, whose chain of permutations runs about twice as fast.
-  // The exchange area is this wave's own staging rows.
-  // (compiled into the mixed-variant kernel only: in the fixed-variant ones
-  // the extra code alone slowed the one-block uniform batch by 8 %)
-  const uint32_t split_n = sorted && V == kMixed ? ctl[CTL_SPLIT_N] : 0u;
-  if constexpr (V == kMixed) {
-    if (front && split_n) {
-      namespace sp = kb::split;
-      uint64_t* area = reinterpret_cast<uint64_t*>(lds + (threadIdx.x & ~63u) * S::kRowDw);
-      uint64_t* zero = area + kSplitGroups * sp::kGroupSlots;
-      if (lane == 0) *zero = 0;
-      __asm__ volatile("" ::: "memory");
-      sp::SplitLane L;
-      sp::setup(L, lane % sp::kGroupLanes, area + (lane / sp::kGroupLanes) * sp::kGroupSlots, zero);
-      const int slot_dw = V == kMixed ? 16 : kb::digest_bytes_of(V) / 4;
-      uint32_t* split_ctr = reinterpret_cast<uint32_t*>(queues + kQueues * (kQueueStrideDw / 2));
-      __builtin_amdgcn_s_setprio(3);
-      for (;;) {
-        uint32_t d = 0;
-        if (lane == 0)
-          d = __hip_atomic_fetch_add(split_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        d = __builtin_amdgcn_readfirstlane(__shfl(d, 0));
-        if (d >= (split_n + kSplitGroups - 1u) / kSplitGroups) break;
-        const uint32_t pos = d * kSplitGroups + lane / sp::kGroupLanes;
-        if (pos < split_n) {
-          const uint32_t i = order[pos];
-          const int var = V == kMixed ? vars[i] : V;
-          uint32_t* o = reinterpret_cast<uint32_t*>(out + static_cast<uint64_t>(i) * stride);
-          if (V == kMixed && var > 3) {
-            Lane z[5];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) z[j] = Lane{0u, 0u};
-            sp::store_words(o, z, 0, slot_dw, L);
-          } else {
-            split_hash<V>(data + offs[i], lens[i], var, o, slot_dw, L);
-          }
-        }
-      }
-      __builtin_amdgcn_s_setprio(0);
-    }
-  }
-  uint32_t qi = 0;  // sub-queues tried so far (bucketed order)
-  for (;;) {
-    // choose the next item; the hashing below appears once in the kernel
-    uint32_t t = 0xFFFFFFFFu;
-    if (!sorted) {
-      uint32_t d = 0;
-      if (lane == 0)
-        d = __hip_atomic_fetch_add(reinterpret_cast<uint32_t*>(queues), 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-      d = __builtin_amdgcn_readfirstlane(__shfl(d, 0));
-      if (d < n_items) t = d;
-    } else {
-      while (qi < kQueues) {
-        const uint32_t x = (home + qi) & (kQueues - 1u);
-        const uint32_t m = n_items > x ? (n_items - x + kQueues - 1u) / kQueues : 0u;
-        unsigned long long old = 0;
-        if (lane == 0)
-          old = __hip_atomic_fetch_add(queues + x * (kQueueStrideDw / 2), step, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t head = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old), 0));
-        const uint32_t tail =
-            __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old >> 32), 0));
-        if (static_cast<uint64_t>(head) + tail < m) {
-          t = x + kQueues * (front ? head : m - 1u - tail);
-          break;
-        }
-        ++qi;
-      }
-    }
-    if (t == 0xFFFFFFFFu) break;
-    const WorkItem it = items[t];
-    if (sorted && front && it.key >= prio_key)
-      __builtin_amdgcn_s_setprio(3);
-    else
-      __builtin_amdgcn_s_setprio(0);
-    // the next message's index and metadata are loaded while this one hashes
-    uint32_t pos = it.begin + lane;
-    uint64_t i = 0, off = 0, len = 0;
-    int var = V;
-    if (pos < it.end) {
-      i = ord ? ord[pos] : pos;
-      off = offs[i];
-      len = lens[i];
-      if constexpr (V == kMixed) var = vars[i];
-    }
-    while (pos < it.end) {
-      const uint32_t pn = pos + 64u;
-      uint64_t in = 0, offn = 0, lenn = 0;
-      int varn = V;
-      if (pn < it.end) {
-        in = ord ? ord[pn] : pn;
-        offn = offs[in];
-        lenn = lens[in];
-        if constexpr (V == kMixed) varn = vars[in];
-      }
-      hash_one<V>(data, off, len, var, i, out, stride, row);
-      pos = pn;
-      i = in;
-      off = offn;
-      len = lenn;
-      var = varn;
-    }
-  }
-  __builtin_amdgcn_s_setprio(0);
 }
 
 // Tree mode.  Level l has m[l] nodes stored from byte offset off[l] of
@@ -575,13 +480,28 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
 }
 
 // ---------------------------------------------------------------------------
-// Scheduler kernels
+// Persistent form: two passes
 // ---------------------------------------------------------------------------
-
-__global__ void k_reset(uint32_t* __restrict__ meta, uint32_t words) {
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < words; k += gridDim.x * blockDim.x)
-    meta[k] = 0u;
-}
+//
+// k_first   a resident grid walks arrival order in 64-message chunks (wave w
+//           takes chunks w, w + W, w + 2W, ... of W waves).  A chunk whose
+//           messages are all one block long is hashed at once: no lane
+//           idles and no ordering could shorten it.  Its digests are held
+//           in registers and stored after the next chunk's loads are
+//           issued, and the next chunk's metadata and block are loaded
+//           while this one is permuted, so every wait falls right after a
+//           permutation.  Any other chunk is deferred: its messages'
+//           block-count keys are counted and its index queued.  The last
+//           workgroup to finish makes the plan for the deferred messages
+//           (bucket starts longest first, queue items, the split range)
+//           and clears the counters the call used.
+// k_second  a resident grid first takes tiles (queue items, and the
+//           counting-sort scatter of the deferred messages into bucketed
+//           order), waits until every tile is done, then hashes: waves pop
+//           queue items (longest first) until the queue is drained.
+//
+// A batch of equal one-block messages is thus hashed in one pass with no
+// sort; the second launch finds nothing to do.
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
@@ -596,39 +516,68 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int V>
 __device__ __forceinline__ uint32_t key_at(const uint64_t* __restrict__ lens,
                                            const uint8_t* __restrict__ vars, uint64_t i) {
   return key_of(blocks_of<V>(lens[i], V == kMixed ? vars[i] : V));
 }
 
-// One 64-message chunk of arrival order (lane 0 always holds a message,
-// `cnt` of the 64 lanes do).  When every message of the chunk has the same
-// length and variant (the common case for uniform batches) the block count
-// is worked out once and one LDS atomic records the chunk; otherwise every
-// lane adds its own key and the chunk's idle lane-slots (cnt * max - sum)
-// are accumulated.  `useful` and `idle` stay wave-uniform.
+// One chunk's metadata in a lane, as the first pass needs it: the length
+// saturates at 2^32 - 1 (a one-block message is shorter than a rate, and any
+// length from 2^32 on has a block count past the last key), and the variant
+// is a register only in the mixed form.  Lanes past the batch load message
+// 0's (every lane issues the same loads); whether a lane holds a message
+// follows from the chunk index.
+struct ChunkMeta {
+  uint64_t off;
+  uint32_t len;
+  int var;
+};
+
+__device__ __forceinline__ bool lane_valid(const PassArgs& a, uint64_t c, uint32_t lane) {
+  return c * 64u + lane < a.n;
+}
+
 template <int V>
-__device__ __forceinline__ void count_chunk(uint64_t len, int var, bool valid, uint32_t cnt,
-                                            uint32_t lane, uint32_t* lhist, uint64_t& useful,
-                                            uint64_t& idle, uint32_t& kmax) {
-  const uint32_t lo0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(len));
-  const uint32_t hi0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(len >> 32));
-  const uint64_t len0 = (static_cast<uint64_t>(hi0) << 32) | lo0;
-  const int var0 = V == kMixed ? __builtin_amdgcn_readfirstlane(var) : V;
-  if (__ballot(valid && (len != len0 || var != var0)) == 0) {
-    const uint32_t key = key_of(blocks_of<V>(len0, var0));
-    if (lane == 0) atomicAdd(&lhist[key], cnt);
-    useful += static_cast<uint64_t>(key) * cnt;
-    kmax = key > kmax ? key : kmax;
-  } else {
-    const uint32_t key = valid ? key_of(blocks_of<V>(len, var)) : 0u;
-    kmax = key > kmax ? key : kmax;
-    if (valid) atomicAdd(&lhist[key], 1u);
-    const uint32_t sm = wave_sum(key), mx = wave_max(key);
-    useful += sm;
-    idle += static_cast<uint64_t>(mx) * cnt - sm;
+__device__ __forceinline__ void load_meta(ChunkMeta& m, const PassArgs& a, uint64_t c,
+                                          uint32_t lane) {
+  const uint64_t i = c * 64u + lane;
+  const uint64_t j = i < a.n ? i : 0u;
+  m.off = a.offs[j];
+  const uint64_t len = a.lens[j];
+  m.len = len >> 32 ? 0xFFFFFFFFu : static_cast<uint32_t>(len);
+  m.var = V == kMixed ? a.vars[j] : V;
+}
+
+// Every valid lane's message is one block long (wave-uniform).
+template <int V>
+__device__ __forceinline__ bool one_block_chunk(const ChunkMeta& m, bool valid) {
+  return __builtin_amdgcn_ballot_w64(valid && m.len >= static_cast<uint32_t>(rate_of<V>(m.var))) == 0;
+}
+
+// The first D bytes of the squeezed state, zero past the digest in the
+// mixed form's 64-byte slots and all zero for a variant out of range.
+template <int V>
+__device__ __forceinline__ void take_digest(uint32_t (&dig)[SpongeShape<V>::kMaxDigestDw],
+                                            const Lane (&A)[25], int var) {
+  using S = SpongeShape<V>;
+  const int DW = V == kMixed ? (var > 3 ? 0 : kb::digest_bytes_rt(var) / 4) : S::kMaxDigestDw;
+#pragma unroll
+  for (int k = 0; k < S::kMaxDigestDw; ++k) {
+    const uint32_t v = (k & 1) ? A[k >> 1].hi : A[k >> 1].lo;
+    dig[k] = k < DW ? v : 0u;
   }
+}
+
+template <int V>
+__device__ __forceinline__ void put_digest(uint8_t* out, const uint32_t (&dig)[SpongeShape<V>::kMaxDigestDw]) {
+  uint32_t* o = reinterpret_cast<uint32_t*>(out);
+#pragma unroll
+  for (int k = 0; k < SpongeShape<V>::kMaxDigestDw; ++k) o[k] = dig[k];
 }
 
 // Inclusive prefix sum over the kBlock threads of a workgroup.
@@ -654,12 +603,8 @@ __device__ __forceinline__ uint32_t item_msgs(uint32_t key, uint32_t steps) {
   return 64u * g;
 }
 
-// The plan: keep
-// arrival order if it idles at most 2 % of the lane slots (and no sort is
-// forced), else bucket starts in descending block count.  Bucket rank
-// r = kKeyBins - 1 - key orders buckets longest first; thread t owns ranks
-// 16t .. 16t+15.  Writes the bucket starts (start[key]), the inclusive prefix
-// of queue items per rank (iend[r]) and the queue size.
+// Bucket rank r = kKeyBins - 1 - key orders buckets longest first; in the
+// plan, thread t owns ranks 16t .. 16t + 15.
 constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
 
 // The first CTL_SPLIT_N positions of the bucketed order (the longest
@@ -670,69 +615,90 @@ constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
 // wave) costs throughput.
 constexpr uint32_t kSplitMinKey = 32;
 
-__device__ void make_plan(uint32_t* __restrict__ hist, const uint32_t* __restrict__ hist_copies,
-                          const uint32_t* __restrict__ partials, uint32_t* __restrict__ start,
-                          uint32_t* __restrict__ iend, uint32_t* __restrict__ ctl, uint64_t n,
-                          uint32_t steps, int force_sort, uint32_t split_cap, uint64_t lanes,
-                          uint32_t* scratch) {
-  __shared__ uint32_t identity, split_n;
+// The plan, made by the first pass's last workgroup once every other one
+// has finished.  Folds the partial histograms and sums, writes the bucket
+// starts (longest first), the split range, the inclusive prefix of queue
+// items per rank and the tile counts, and clears every counter and partial
+// this call used, so the next call starts from zero.
+__device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
+  uint32_t* const meta = a.meta;
+  uint32_t* const ctl = meta + M_CTL;
+  uint32_t* const sync = meta + M_SYNC;
+  __shared__ uint32_t s_split, s_ndef;
   const uint32_t t = threadIdx.x;
-  uint64_t useful = 0, idle = 0;
-  uint32_t maxkey = 0;
+  uint64_t useful = 0;
+  uint32_t maxkey = 0, dirty = 0;
 #pragma unroll
   for (uint32_t c = 0; c < kCopies; ++c) {
-    const uint32_t* pc = partials + c * kPartialWords;
-    useful += *reinterpret_cast<const unsigned long long*>(pc + P_USEFUL);
-    idle += *reinterpret_cast<const unsigned long long*>(pc + P_IDLE);
-    maxkey = pc[P_MAXKEY] > maxkey ? pc[P_MAXKEY] : maxkey;
+    const uint32_t* pc = meta + M_PARTIALS + c * kLine;
+    const uint64_t u = (static_cast<uint64_t>(load_relaxed(pc + P_USEFUL + 1)) << 32) |
+                       load_relaxed(pc + P_USEFUL);
+    useful += u;
+    const uint32_t mk = load_relaxed(pc + P_MAXKEY);
+    maxkey = mk > maxkey ? mk : maxkey;
+    dirty |= load_relaxed(pc + P_DIRTY) ? 1u << c : 0u;
+  }
+  // (read into a scalar register: the branch on it below must be uniform in
+  // the compiler's view, since barriers follow it)
+  const uint32_t ndef_chunks = __builtin_amdgcn_readfirstlane(load_relaxed(&sync[SY_DEFER * kLine]));
+  __syncthreads();  // every thread has read the partials and counters
+  if (t < kCopies) {
+    uint32_t* pc = meta + M_PARTIALS + t * kLine;
+    pc[P_USEFUL] = pc[P_USEFUL + 1] = pc[P_MAXKEY] = pc[P_DIRTY] = 0u;
   }
   if (t == 0) {
-    *reinterpret_cast<unsigned long long*>(&ctl[CTL_USEFUL]) = useful;
-    *reinterpret_cast<unsigned long long*>(&ctl[CTL_IDLE]) = idle;
+    sync[SY_TICKET * kLine] = 0u;
+    sync[SY_DEFER * kLine] = 0u;
+    sync[SY_CLAIM * kLine] = 0u;
+    sync[SY_DONE * kLine] = 0u;
+    ctl[CTL_SPIN_LIMIT] = 0u;
     ctl[CTL_MAXKEY] = maxkey;
+    ctl[CTL_USEFUL] = static_cast<uint32_t>(useful);
+    ctl[CTL_USEFUL + 1] = static_cast<uint32_t>(useful >> 32);
+    ctl[CTL_NDEF_CHUNKS] = ndef_chunks;
   }
-  const uint64_t avg = useful / (n ? n : 1);
-  if (t == 0) {
-    identity = (!force_sort && idle * 50u <= useful) ? 1u : 0u;
-    ctl[CTL_IDENTITY] = identity;
-    ctl[CTL_PRIO_KEY] = static_cast<uint32_t>(2u * avg + 2u);
-    if (identity) {
-      const uint32_t per = item_msgs(avg > 0xFFFFu ? 0xFFFFu : static_cast<uint32_t>(avg), 8u);
-      ctl[CTL_ID_PER] = per;
-      ctl[CTL_NITEMS] = static_cast<uint32_t>((n + per - 1) / per);
+  if (ndef_chunks == 0) {  // every chunk was hashed by the first pass
+    if (t == 0) {
+      ctl[CTL_NITEMS] = ctl[CTL_TILES] = ctl[CTL_ITEM_TILES] = ctl[CTL_SPLIT_N] = 0u;
+      ctl[CTL_PRIO_KEY] = 0xFFFFFFFFu;
     }
+    return;
   }
-  __syncthreads();
-  if (identity) return;
-  // This thread's ranks are the 16 consecutive keys lo .. lo + 15 (64-byte
-  // aligned): fold the copies with 16-byte loads, all issued before use.
+  // Fold the dirty copies for this thread's 16 consecutive keys lo .. lo + 15
+  // (64-byte aligned) with 16-byte loads, all issued before use, and clear them.
   static_assert(kRanksPerThread == 16, "four 16-byte loads per copy");
   const uint32_t lo = kKeyBins - kRanksPerThread * (t + 1u);
   uint4 part[kCopies][4];
 #pragma unroll
   for (uint32_t k = 0; k < kCopies; ++k) {
-    const uint4* src = reinterpret_cast<const uint4*>((k ? hist_copies + (k - 1) * kKeyBins : hist) + lo);
+    const uint4* src = reinterpret_cast<const uint4*>(meta + M_HIST + k * kKeyBins + lo);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) part[k][v] = src[v];
+    for (int v = 0; v < 4; ++v) part[k][v] = (dirty >> k) & 1u ? src[v] : make_uint4(0u, 0u, 0u, 0u);
   }
   uint32_t byk[kRanksPerThread];  // folded count of key lo + i
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    uint4 a = part[0][v];
+    uint4 s = part[0][v];
 #pragma unroll
     for (uint32_t k = 1; k < kCopies; ++k) {
-      a.x += part[k][v].x;
-      a.y += part[k][v].y;
-      a.z += part[k][v].z;
-      a.w += part[k][v].w;
+      s.x += part[k][v].x;
+      s.y += part[k][v].y;
+      s.z += part[k][v].z;
+      s.w += part[k][v].w;
     }
-    byk[4 * v] = a.x;
-    byk[4 * v + 1] = a.y;
-    byk[4 * v + 2] = a.z;
-    byk[4 * v + 3] = a.w;
-    // the folded histogram, read by k_fill and the per-bucket form
-    reinterpret_cast<uint4*>(hist + lo)[v] = a;
+    byk[4 * v] = s.x;
+    byk[4 * v + 1] = s.y;
+    byk[4 * v + 2] = s.z;
+    byk[4 * v + 3] = s.w;
+    reinterpret_cast<uint4*>(meta + M_FOLD + lo)[v] = s;
   }
+#pragma unroll
+  for (uint32_t k = 0; k < kCopies; ++k)
+    if ((dirty >> k) & 1u) {
+      uint4* dst = reinterpret_cast<uint4*>(meta + M_HIST + k * kKeyBins + lo);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dst[v] = make_uint4(0u, 0u, 0u, 0u);
+    }
   uint32_t cnt[kRanksPerThread], st[kRanksPerThread], c_sum = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
@@ -740,35 +706,41 @@ __device__ void make_plan(uint32_t* __restrict__ hist, const uint32_t* __restric
     cnt[q] = key ? byk[kRanksPerThread - 1u - q] : 0u;
     c_sum += cnt[q];
   }
-  uint32_t c_base = block_inclusive_scan(c_sum, scratch) - c_sum;
+  const uint32_t c_incl = block_inclusive_scan(c_sum, scratch);
+  uint32_t c_base = c_incl - c_sum;
+  if (t == kBlock - 1) s_ndef = c_incl;
+  __syncthreads();
+  const uint32_t ndef = __builtin_amdgcn_readfirstlane(s_ndef);  // deferred messages
+  const uint64_t avg = useful / (ndef ? ndef : 1u);
   // bucket starts; the split range ends where the keys drop below kmin
-  const uint64_t per_lane = 2u * useful / (lanes ? lanes : 1u);
+  const uint64_t per_lane = 2u * useful / (a.lanes ? a.lanes : 1u);
   uint64_t kmin64 = 4u * avg > kSplitMinKey ? 4u * avg : kSplitMinKey;
   if (per_lane > kmin64) kmin64 = per_lane;
   const uint32_t kmin = kmin64 < kKeyBins - 1u ? static_cast<uint32_t>(kmin64) : kKeyBins - 1u;
-  if (t == 0) split_n = static_cast<uint32_t>(n);  // every key at least kmin
+  if (t == 0) s_split = ndef;  // every key at least kmin
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
     st[q] = c_base;
-    start[key] = c_base;
+    meta[M_START + key] = c_base;
     c_base += cnt[q];
   }
   __syncthreads();
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
-    if (key == kmin - 1u) split_n = st[q];  // messages in buckets of key >= kmin
+    if (key == kmin - 1u) s_split = st[q];  // messages in buckets of key >= kmin
   }
   __syncthreads();
-  const uint32_t split = split_n < split_cap ? split_n : split_cap;
+  const uint32_t split_all = __builtin_amdgcn_readfirstlane(s_split);
+  const uint32_t split = split_all < a.split_cap ? split_all : a.split_cap;
   // queue items over the positions past the split range
   uint32_t items[kRanksPerThread], it_sum = 0;
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
     const uint32_t b = st[q] > split ? st[q] : split, e = st[q] + cnt[q];
-    const uint32_t per = item_msgs(key, steps);
+    const uint32_t per = item_msgs(key, a.steps);
     items[q] = e > b ? (e - b + per - 1u) / per : 0u;
     it_sum += items[q];
   }
@@ -776,229 +748,426 @@ __device__ void make_plan(uint32_t* __restrict__ hist, const uint32_t* __restric
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     it_run += items[q];
-    iend[kRanksPerThread * t + q] = it_run;
+    meta[M_IEND + kRanksPerThread * t + q] = it_run;
   }
+  // the second pass's scatter cursors, queues and SIMD flags start at zero
+  for (uint32_t k = t; k < kKeyBins / 4; k += kBlock)
+    reinterpret_cast<uint4*>(meta + M_CURSOR)[k] = make_uint4(0u, 0u, 0u, 0u);
+  for (uint32_t k = t; k < kQueueAreaDw / 4; k += kBlock)
+    reinterpret_cast<uint4*>(meta + M_QUEUES)[k] = make_uint4(0u, 0u, 0u, 0u);
+  for (uint32_t k = t; k < kSimdSlots / 4; k += kBlock)
+    reinterpret_cast<uint4*>(meta + M_SIMD)[k] = make_uint4(0u, 0u, 0u, 0u);
   if (t == kBlock - 1) {
+    const uint32_t item_tiles = (it_run + kBlock - 1) / kBlock;
     ctl[CTL_NITEMS] = it_run;
     ctl[CTL_SPLIT_N] = split;
+    ctl[CTL_PRIO_KEY] = static_cast<uint32_t>(2u * avg + 2u);
+    ctl[CTL_ITEM_TILES] = item_tiles;
+    ctl[CTL_TILES] = item_tiles + (ndef_chunks + kScatterChunks - 1) / kScatterChunks;
   }
 }
 
-// One workgroup makes the plan once the histogram is complete.  (Folding
-// this into the last workgroup of k_count costs more than the launch: every
-// workgroup must then fence and wait for its histogram atomics before
-// drawing a ticket.)
-__global__ __launch_bounds__(kBlock) void k_plan(uint32_t* __restrict__ hist,
-                                                 const uint32_t* __restrict__ hist_copies,
-                                                 const uint32_t* __restrict__ partials,
-                                                 uint32_t* __restrict__ start,
-                                                 uint32_t* __restrict__ iend,
-                                                 uint32_t* __restrict__ ctl, uint64_t n,
-                                                 uint32_t steps, int force_sort,
-                                                 uint32_t split_cap, uint64_t lanes) {
-  __shared__ uint32_t scratch[kBlock];
-  make_plan(hist, hist_copies, partials, start, iend, ctl, n, steps, force_sort, split_cap, lanes,
-            scratch);
-}
-
-// Two 64-message chunks of arrival order, messages 2 lane and 2 lane + 1 of
-// a 128-message pair in each lane (lanes 0-31 hold the first chunk, 32-63
-// the second).  Same accounting as count_chunk, with one LDS atomic for the
-// pair when all 128 lengths and variants are equal.
+// Waves per SIMD the first pass is compiled for: three for the fixed
+// variants (the register allocator then fits the permutation, the next
+// chunk's block in flight and two chunks of metadata in 168 VGPRs without
+// spilling); the mixed form needs more registers, and SHAKE128's 168-byte
+// rate more LDS, so those hold two.
 template <int V>
-__device__ __forceinline__ void count_pair(uint64_t la, uint64_t lb, int va, int vb, uint32_t lane,
-                                           uint32_t* lhist, uint64_t& useful, uint64_t& idle,
-                                           uint32_t& kmax) {
-  const uint32_t lo0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(la));
-  const uint32_t hi0 = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(la >> 32));
-  const uint64_t len0 = (static_cast<uint64_t>(hi0) << 32) | lo0;
-  const int var0 = V == kMixed ? __builtin_amdgcn_readfirstlane(va) : V;
-  if (__ballot(la != len0 || lb != len0 || va != var0 || vb != var0) == 0) {
-    const uint32_t key = key_of(blocks_of<V>(len0, var0));
-    if (lane == 0) atomicAdd(&lhist[key], 128u);
-    useful += static_cast<uint64_t>(key) * 128u;
-    kmax = key > kmax ? key : kmax;
-  } else {
-    const uint32_t ka = key_of(blocks_of<V>(la, va)), kb = key_of(blocks_of<V>(lb, vb));
-    atomicAdd(&lhist[ka], 1u);
-    atomicAdd(&lhist[kb], 1u);
-    uint32_t sm = ka + kb, mx = ka > kb ? ka : kb;
-    kmax = mx > kmax ? mx : kmax;
-    for (int d = 16; d >= 1; d >>= 1) {  // within each half of the wave
-      sm += __shfl_xor(sm, d);
-      const uint32_t o = __shfl_xor(mx, d);
-      mx = o > mx ? o : mx;
-    }
-    const uint32_t s0 = __builtin_amdgcn_readlane(sm, 0), s1 = __builtin_amdgcn_readlane(sm, 32);
-    const uint32_t m0 = __builtin_amdgcn_readlane(mx, 0), m1 = __builtin_amdgcn_readlane(mx, 32);
-    useful += static_cast<uint64_t>(s0) + s1;
-    idle += (64ull * m0 - s0) + (64ull * m1 - s1);
-  }
-}
+constexpr int kFirstWaves = V == kMixed || V == kShake128 ? 2 : 3;
 
-// Histogram of block-count keys and the lane slots arrival order would
-// idle, into copy blockIdx.x mod kCopies of the histogram and the control
-// partials.  A wave takes kCountUnroll whole 128-message pairs per pass, two
-// adjacent lengths per lane, and issues all their loads before using any;
-// the chunks past the last whole pass (and the ragged last chunk) are taken
-// one at a time with bounds checks.
-constexpr int kCountUnroll = 8;
-
+// First pass (see above).  a.hash == 0 defers every chunk (the per-bucket
+// form hashes nothing here).
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_count(const uint64_t* __restrict__ lens,
-                                                  const uint8_t* __restrict__ vars, uint64_t n,
-                                                  uint32_t* __restrict__ hist,
-                                                  uint32_t* __restrict__ hist_copies,
-                                                  uint32_t* __restrict__ partials) {
-  __shared__ uint32_t lhist[kKeyBins];
-  __shared__ unsigned long long luseful, lidle;
-  __shared__ uint32_t lmax;
-  for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock) lhist[k] = 0u;
+__global__ __launch_bounds__(kBlock, kFirstWaves<V>) void k_first(PassArgs a) {
+  using S = SpongeShape<V>;
+  a.n = pass_count(a);
+  __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
+  __shared__ uint32_t lhist[kLdsBins];
+  __shared__ unsigned long long luseful;
+  __shared__ uint32_t lmax, last;
+  uint32_t* const row = lds + threadIdx.x * S::kRowDw;
+  uint32_t* const hist = a.meta + M_HIST + (blockIdx.x % kCopies) * kKeyBins;
+  uint32_t* const sync = a.meta + M_SYNC;
+  for (uint32_t k = threadIdx.x; k < kLdsBins; k += kBlock) lhist[k] = 0u;
   if (threadIdx.x == 0) {
     luseful = 0ull;
-    lidle = 0ull;
     lmax = 0u;
   }
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t waves = static_cast<uint64_t>(gridDim.x) * (kBlock / 64);
-  const uint64_t wave_id = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
-  uint64_t useful = 0, idle = 0;
+  const uint64_t nch = (a.n + 63u) / 64u;
+  const uint64_t W = static_cast<uint64_t>(gridDim.x) * (kBlock / 64);
+  const uint64_t c0 = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64u;
+  // Deferred chunks not yet in the global list: lane k holds entry k.
+  uint32_t dbuf = 0, dcnt = 0;
+  uint64_t useful = 0;  // block counts of the deferred messages (wave-uniform)
   uint32_t kmax = 0;
-  const uint64_t passes = (n / 128u) / kCountUnroll;  // passes of whole pairs
-  for (uint64_t g = wave_id; g < passes; g += waves) {
-    uint64_t la[kCountUnroll], lb[kCountUnroll];
-    int va[kCountUnroll], vb[kCountUnroll];
+  auto flush = [&]() {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&sync[SY_DEFER * kLine], dcnt);
+    base = __builtin_amdgcn_readfirstlane(__shfl(base, 0));
+    if (lane < dcnt) a.deferred[base + lane] = dbuf;
+    dcnt = 0;
+  };
+  auto defer = [&](const ChunkMeta& m, uint64_t c) {
+    const bool valid = lane_valid(a, c, lane);
+    const uint32_t key = valid ? key_of(blocks_of<V>(m.len, m.var)) : 0u;
+    if (valid) {
+      if (key < kLdsBins)
+        atomicAdd(&lhist[key], 1u);
+      else
+        atomicAdd(&hist[key], 1u);
+    }
+    useful += __builtin_amdgcn_readfirstlane(wave_sum(key));
+    const uint32_t mx = __builtin_amdgcn_readfirstlane(wave_max(key));
+    kmax = mx > kmax ? mx : kmax;
+    if (lane == dcnt) dbuf = static_cast<uint32_t>(c);
+    if (++dcnt == 64u) flush();
+  };
+  // one-block messages only: the length is the block's message bytes
+  auto load = [&](kb::BlockChunks<V>& b, const ChunkMeta& m, uint64_t c) {
+    kb::load_block<V>(b, a.data + m.off, lane_valid(a, c, lane) ? m.len : 0u);
+  };
+  ChunkMeta m0, m1;
+  kb::BlockChunks<V> bc;
+  load_meta<V>(m0, a, c0, lane);
+  load_meta<V>(m1, a, c0 + W, lane);
+  bool h0 = false;
+  if (c0 < nch) {
+    h0 = a.hash && one_block_chunk<V>(m0, lane_valid(a, c0, lane));
+    if (h0)
+      load(bc, m0, c0);
+    else
+      defer(m0, c0);
+  }
+  uint32_t dig[S::kMaxDigestDw > 0 ? S::kMaxDigestDw : 1];
+  // dig holds the digests of chunk `pend` until the next chunk is staged
+  uint64_t pend = ~0ull;
+  auto put = [&]() {
+    if constexpr (V < kShake128) {
+      if (pend != ~0ull && lane_valid(a, pend, lane)) put_digest<V>(a.out + (pend * 64u + lane) * a.stride, dig);
+    }
+    pend = ~0ull;
+  };
+  for (uint64_t c = c0; c < nch; c += W) {
+    Lane A[25];
+    if (h0) {  // stage chunk c's block and absorb it into the zero state
+      uint32_t w[S::kMaxRateDw];
+      kb::stage_block<V>(row, bc, lane_valid(a, c, lane) ? m0.len : 0u, rate_of<V>(m0.var), true, w);
+      const int RW = rate_of<V>(m0.var) / 4;
 #pragma unroll
-    for (int u = 0; u < kCountUnroll; ++u) {
-      const uint64_t i = (g * kCountUnroll + u) * 128u + 2u * lane;
-      la[u] = lens[i];
-      lb[u] = lens[i + 1];
-      va[u] = vb[u] = V;
-      if constexpr (V == kMixed) {
-        va[u] = vars[i];
-        vb[u] = vars[i + 1];
+      for (int k = 0; k < 50; ++k) {
+        const uint32_t v = (k < S::kMaxRateDw && k < RW) ? w[k < S::kMaxRateDw ? k : 0] : 0u;
+        if (k & 1)
+          A[k >> 1].hi = v;
+        else
+          A[k >> 1].lo = v;
       }
     }
-#pragma unroll
-    for (int u = 0; u < kCountUnroll; ++u)
-      count_pair<V>(la[u], lb[u], va[u], vb[u], lane, lhist, useful, idle, kmax);
+    put();  // the previous chunk's digests: issued after the wait above, before the loads below
+    // chunk c + W: decide, and start its block's loads; metadata of c + 2W
+    const uint64_t c1 = c + W;
+    bool h1 = false;
+    if (c1 < nch) {
+      h1 = a.hash && one_block_chunk<V>(m1, lane_valid(a, c1, lane));
+      if (h1)
+        load(bc, m1, c1);
+      else
+        defer(m1, c1);
+    }
+    ChunkMeta m2;
+    load_meta<V>(m2, a, c1 + W, lane);
+    if (h0) {
+      kb::keccak_rounds_0_22(A);
+      kb::keccak_round(A, 23);
+      if constexpr (V >= kShake128) {
+        if (lane_valid(a, c, lane)) kb::squeeze_xof<V>(A, a.out + (c * 64u + lane) * a.stride, a.stride);
+      } else {
+        take_digest<V>(dig, A, m0.var);
+        pend = c;
+      }
+    }
+    m0 = m1;
+    m1 = m2;
+    h0 = h1;
   }
-  for (uint64_t c = passes * kCountUnroll * 2u + wave_id; c * 64u < n; c += waves) {
-    const uint64_t i = c * 64u + lane;
-    const bool valid = i < n;
-    const uint64_t len = valid ? lens[i] : 0u;
-    const int var = V == kMixed ? (valid ? vars[i] : 0) : V;
-    const uint32_t cnt = n - c * 64u < 64u ? static_cast<uint32_t>(n - c * 64u) : 64u;
-    count_chunk<V>(len, var, valid, cnt, lane, lhist, useful, idle, kmax);
-  }
+  put();
+  if (dcnt) flush();
   if (lane == 0) {
-    atomicAdd(&luseful, static_cast<unsigned long long>(useful));
-    atomicAdd(&lidle, static_cast<unsigned long long>(idle));
+    if (useful) atomicAdd(&luseful, static_cast<unsigned long long>(useful));
+    atomicMax(&lmax, kmax);
   }
-  atomicMax(&lmax, kmax);
   __syncthreads();
-  const uint32_t copy = blockIdx.x % kCopies;
-  uint32_t* h = copy ? hist_copies + (copy - 1u) * kKeyBins : hist;
-  for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock)
-    if (lhist[k]) atomicAdd(&h[k], lhist[k]);
-  if (threadIdx.x == 0) {
-    uint32_t* pc = partials + copy * kPartialWords;
+  for (uint32_t k = threadIdx.x; k < kLdsBins; k += kBlock)
+    if (lhist[k]) atomicAdd(&hist[k], lhist[k]);
+  if (threadIdx.x == 0 && luseful) {
+    uint32_t* pc = a.meta + M_PARTIALS + (blockIdx.x % kCopies) * kLine;
     atomicAdd(reinterpret_cast<unsigned long long*>(pc + P_USEFUL), luseful);
-    atomicAdd(reinterpret_cast<unsigned long long*>(pc + P_IDLE), lidle);
     atomicMax(pc + P_MAXKEY, lmax);
+    atomicOr(pc + P_DIRTY, 1u);
   }
+  // the last workgroup to get here makes the plan
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&sync[SY_TICKET * kLine], 1u) == gridDim.x - 1u ? 1u : 0u;
+  __syncthreads();
+  // values broadcast through LDS are read with readfirstlane wherever a
+  // branch on them precedes a barrier: the compiler must see the branch as
+  // uniform, or it may restructure the barriers into divergent code
+  if (!__builtin_amdgcn_readfirstlane(last)) return;
+  __threadfence();
+  make_plan(a, lds);
 }
 
-// Queue item t: its bucket (the smallest rank r with iend[r] > t) and its
-// range of positions in the bucketed order.
-__device__ __forceinline__ void items_block(uint32_t blk, const uint32_t* __restrict__ hist,
-                                            const uint32_t* __restrict__ start,
-                                            const uint32_t* __restrict__ iend,
-                                            const uint32_t* __restrict__ ctl, uint64_t n,
-                                            uint32_t steps, WorkItem* __restrict__ items) {
-  const uint32_t t = blk * kBlock + threadIdx.x;
-  if (t >= ctl[CTL_NITEMS]) return;
-  if (ctl[CTL_IDENTITY]) {
-    const uint64_t per = ctl[CTL_ID_PER];
-    const uint64_t b = t * per, e = b + per < n ? b + per : n;
-    items[t] = WorkItem{static_cast<uint32_t>(b), static_cast<uint32_t>(e), 0u, 0u};
-    return;
-  }
+// Queue item q of the second pass: its bucket (the smallest rank r with
+// iend[r] > q) and its range of positions in the bucketed order.
+__device__ __forceinline__ void items_tile(const PassArgs& a, uint32_t tile) {
+  const uint32_t* meta = a.meta;
+  const uint32_t* ctl = meta + M_CTL;
+  const uint32_t q = tile * kBlock + threadIdx.x;
+  if (q >= ctl[CTL_NITEMS]) return;
+  const uint32_t* iend = meta + M_IEND;
   uint32_t lo = 0, hi = kKeyBins - 1;
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (iend[mid] > t)
+    if (iend[mid] > q)
       hi = mid;
     else
       lo = mid + 1;
   }
   const uint32_t key = kKeyBins - 1u - lo;
-  const uint32_t per = item_msgs(key, steps);
+  const uint32_t per = item_msgs(key, a.steps);
   const uint32_t first_item = lo ? iend[lo - 1] : 0u;
   const uint32_t split = ctl[CTL_SPLIT_N];  // positions before it are split work
-  const uint32_t b = (start[key] > split ? start[key] : split) + (t - first_item) * per;
-  const uint32_t bucket_end = start[key] + hist[key];
-  items[t] = WorkItem{b, b + per < bucket_end ? b + per : bucket_end, key, 0u};
+  const uint32_t start = meta[M_START + key];
+  const uint32_t b = (start > split ? start : split) + (q - first_item) * per;
+  const uint32_t bucket_end = start + meta[M_FOLD + key];
+  a.items[q] = WorkItem{b, b + per < bucket_end ? b + per : bucket_end, key, 0u};
 }
 
-// Counting-sort scatter: workgroup w handles messages [w * tile, (w+1) * tile),
-// reserves one range per non-empty bucket with a single global atomic, and
-// ranks its messages inside each range with LDS atomics.
+// Counting-sort scatter of kScatterChunks deferred chunks: one global
+// atomic per non-empty bucket reserves the tile's range, LDS atomics rank
+// the messages inside it.
 template <int V>
-__device__ __forceinline__ void scatter_block(uint32_t blk, const uint64_t* __restrict__ lens,
-                                              const uint8_t* __restrict__ vars, uint64_t n,
-                                              const uint32_t* __restrict__ start,
-                                              uint32_t* __restrict__ cursor,
-                                              const uint32_t* __restrict__ ctl,
-                                              uint32_t* __restrict__ order) {
-  if (ctl[CTL_IDENTITY]) return;
-  __shared__ uint32_t lcount[kKeyBins];
-  __shared__ uint32_t lbase[kKeyBins];
+__device__ __forceinline__ void scatter_tile(const PassArgs& a, uint32_t tile, uint32_t* lcount,
+                                             uint32_t* lbase) {
+  constexpr uint32_t kPer = kScatterChunks * 64u / kBlock;  // messages per thread
+  const uint32_t nchunks = a.meta[M_CTL + CTL_NDEF_CHUNKS];
   for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock) lcount[k] = 0u;
   __syncthreads();
-  const uint64_t first = static_cast<uint64_t>(blk) * kScatterTile;
-  const uint64_t last = first + kScatterTile < n ? first + kScatterTile : n;
-  uint32_t keys[kScatterTile / kBlock];
+  const uint32_t first = tile * kScatterChunks;
+  uint32_t keys[kPer];
+  uint64_t msg[kPer];
 #pragma unroll
-  for (int q = 0; q < kScatterTile / kBlock; ++q) {
-    const uint64_t i = first + static_cast<uint64_t>(q) * kBlock + threadIdx.x;
-    keys[q] = i < last ? key_at<V>(lens, vars, i) : 0u;
-    if (i < last) atomicAdd(&lcount[keys[q]], 1u);
+  for (uint32_t q = 0; q < kPer; ++q) {
+    const uint32_t slot = (q * kBlock + threadIdx.x) / 64u, lane = threadIdx.x & 63u;
+    msg[q] = ~0ull;
+    keys[q] = 0u;
+    if (first + slot < nchunks) {
+      const uint64_t i = static_cast<uint64_t>(a.deferred[first + slot]) * 64u + lane;
+      if (i < a.n) {
+        msg[q] = i;
+        keys[q] = key_at<V>(a.lens, a.vars, i);
+        atomicAdd(&lcount[keys[q]], 1u);
+      }
+    }
   }
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < kKeyBins; k += kBlock) {
     const uint32_t c = lcount[k];
-    lbase[k] = c ? start[k] + atomicAdd(&cursor[k], c) : 0u;
+    lbase[k] = c ? a.meta[M_START + k] + atomicAdd(&a.meta[M_CURSOR + k], c) : 0u;
     lcount[k] = 0u;
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kScatterTile / kBlock; ++q) {
-    const uint64_t i = first + static_cast<uint64_t>(q) * kBlock + threadIdx.x;
-    if (i < last) {
+  for (uint32_t q = 0; q < kPer; ++q)
+    if (msg[q] != ~0ull) {
       const uint32_t rank = atomicAdd(&lcount[keys[q]], 1u);
-      order[lbase[keys[q]] + rank] = static_cast<uint32_t>(i);
+      a.order[lbase[keys[q]] + rank] = static_cast<uint32_t>(msg[q]);
     }
-  }
+  __syncthreads();  // the LDS arrays are reused by the next tile
 }
 
-// Queue items and the scatter in one launch (both depend only on the plan):
-// workgroups [0, iblocks) write queue items, the rest scatter the order.
+// A second-pass workgroup waits at most this many sleeps for the tiles of
+// the others (about a second); the tiles need microseconds, so the bound is
+// only a guard against a wait that could never end.
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Second pass (see above).  On each SIMD one wave (the first to claim the
+// SIMD's flag) takes items from the front at raised issue priority while
+// they are long, so the long absorb chains that bound the makespan run back
+// to back at full rate; the other resident waves take the shortest items
+// from the back and fill the issue slots the front wave leaves idle.  Both
+// ends of a sub-queue advance one packed 64-bit counter, so no item is taken
+// twice.  A wave drains the sub-queue of its own XCD first and then the
+// others in turn, so every item is taken whatever the mapping of waves to
+// XCDs, and every wave leaves once all sub-queues are empty.
 template <int V>
-__global__ __launch_bounds__(kBlock) void k_fill(const uint64_t* __restrict__ lens,
-                                                 const uint8_t* __restrict__ vars, uint64_t n,
-                                                 const uint32_t* __restrict__ hist,
-                                                 const uint32_t* __restrict__ start,
-                                                 uint32_t* __restrict__ cursor,
-                                                 const uint32_t* __restrict__ iend,
-                                                 const uint32_t* __restrict__ ctl, uint32_t steps,
-                                                 uint32_t iblocks, WorkItem* __restrict__ items,
-                                                 uint32_t* __restrict__ order) {
-  if (blockIdx.x < iblocks)
-    items_block(blockIdx.x, hist, start, iend, ctl, n, steps, items);
-  else
-    scatter_block<V>(blockIdx.x - iblocks, lens, vars, n, start, cursor, ctl, order);
+__global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
+  using S = SpongeShape<V>;
+  a.n = pass_count(a);
+  constexpr uint32_t kStageDw = kBlock * S::kRowDw;
+  constexpr uint32_t kLdsDw = kStageDw > 2 * kKeyBins ? kStageDw : 2 * kKeyBins;
+  __shared__ __align__(16) uint32_t lds[kLdsDw];
+  __shared__ uint32_t s_tile, s_gave_up;
+  static_assert(2 * (kSplitGroups * kb::split::kGroupSlots + 1) <= 64 * S::kRowDw,
+                "a wave's staging rows hold its split exchange area");
+  const uint32_t* ctl = a.meta + M_CTL;
+  uint32_t* const sync = a.meta + M_SYNC;
+  const uint32_t tiles = ctl[CTL_TILES];
+  if (tiles == 0) return;  // the first pass hashed everything
+  const uint32_t item_tiles = ctl[CTL_ITEM_TILES];
+  // Tiles are claimed one at a time from a counter.  One thread claims and
+  // reports; the loop condition is a scalar read after a barrier, so the
+  // loop (with the barriers in it) is uniform as the compiler sees it.
+  if (threadIdx.x == 0) s_tile = atomicAdd(&sync[SY_CLAIM * kLine], 1u);
+  __syncthreads();
+  uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
+  while (tile < tiles) {
+    __syncthreads();  // every thread has read s_tile
+    if (tile < item_tiles)
+      items_tile(a, tile);
+    else
+      scatter_tile<V>(a, tile - item_tiles, lds, lds + kKeyBins);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      atomicAdd(&sync[SY_DONE * kLine], 1u);
+      s_tile = atomicAdd(&sync[SY_CLAIM * kLine], 1u);
+    }
+    __syncthreads();
+    tile = __builtin_amdgcn_readfirstlane(s_tile);
+  }
+  if (!a.hash) return;
+  // Wait for the tiles of the other workgroups.  Every claimed tile is held
+  // by a running workgroup that finishes it without waiting on anything, so
+  // the count reaches `tiles` whichever workgroups are resident.
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (load_relaxed(&sync[SY_DONE * kLine]) < tiles && spins < kSpinLimit) {
+      __builtin_amdgcn_s_sleep(8);
+      ++spins;
+    }
+    s_gave_up = spins >= kSpinLimit ? 1u : 0u;
+    if (s_gave_up) a.meta[M_CTL + CTL_SPIN_LIMIT] = 1u;
+  }
+  __syncthreads();
+  if (__builtin_amdgcn_readfirstlane(s_gave_up)) return;
+  __threadfence();  // the items and the bucketed order are visible from here on
+
+  uint32_t* row = lds + threadIdx.x * S::kRowDw;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t n_items = ctl[CTL_NITEMS];
+  const uint32_t prio_key = ctl[CTL_PRIO_KEY];
+  unsigned long long* const queues = reinterpret_cast<unsigned long long*>(a.meta + M_QUEUES);
+  uint32_t claim = 0;
+  if (lane == 0) claim = atomicCAS(&a.meta[M_SIMD + simd_slot()], 0u, 1u) == 0u ? 1u : 0u;
+  const bool front = __builtin_amdgcn_readfirstlane(__shfl(claim, 0)) != 0u;
+  const unsigned long long step = 1ull << (front ? 0 : 32);
+  const uint32_t home = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kQueues - 1u);
+  // Split items first: the front waves hash the longest messages (bucketed
+  // positions [0, split_n)) eight at a time, one per 8-lane group, in the
+  // lane-split form, whose chain of permutations runs about twice as fast.
+  // The exchange area is this wave's own staging rows.
+  // (compiled into the mixed-variant kernel only: in the fixed-variant ones
+  // the extra code alone slowed the one-block uniform batch by 8 %)
+  const uint32_t split_n = V == kMixed ? ctl[CTL_SPLIT_N] : 0u;
+  if constexpr (V == kMixed) {
+    if (front && split_n) {
+      namespace sp = kb::split;
+      uint64_t* area = reinterpret_cast<uint64_t*>(lds + (threadIdx.x & ~63u) * S::kRowDw);
+      uint64_t* zero = area + kSplitGroups * sp::kGroupSlots;
+      if (lane == 0) *zero = 0;
+      __asm__ volatile("" ::: "memory");
+      sp::SplitLane L;
+      sp::setup(L, lane % sp::kGroupLanes, area + (lane / sp::kGroupLanes) * sp::kGroupSlots, zero);
+      const int slot_dw = 16;
+      uint32_t* split_ctr = reinterpret_cast<uint32_t*>(queues + kQueues * (kLine / 2));
+      __builtin_amdgcn_s_setprio(3);
+      for (;;) {
+        uint32_t d = 0;
+        if (lane == 0)
+          d = __hip_atomic_fetch_add(split_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        d = __builtin_amdgcn_readfirstlane(__shfl(d, 0));
+        if (d >= (split_n + kSplitGroups - 1u) / kSplitGroups) break;
+        const uint32_t pos = d * kSplitGroups + lane / sp::kGroupLanes;
+        if (pos < split_n) {
+          const uint32_t i = a.order[pos];
+          const int var = a.vars[i];
+          uint32_t* o = reinterpret_cast<uint32_t*>(a.out + static_cast<uint64_t>(i) * a.stride);
+          if (var > 3) {
+            Lane z[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) z[j] = Lane{0u, 0u};
+            sp::store_words(o, z, 0, slot_dw, L);
+          } else {
+            split_hash<V>(a.data + a.offs[i], a.lens[i], var, o, slot_dw, L);
+          }
+        }
+      }
+      __builtin_amdgcn_s_setprio(0);
+    }
+  }
+  uint32_t qi = 0;  // sub-queues tried so far
+  for (;;) {
+    // choose the next item; the hashing below appears once in the kernel
+    uint32_t t = 0xFFFFFFFFu;
+    while (qi < kQueues) {
+      const uint32_t x = (home + qi) & (kQueues - 1u);
+      const uint32_t m = n_items > x ? (n_items - x + kQueues - 1u) / kQueues : 0u;
+      unsigned long long old = 0;
+      if (lane == 0)
+        old = __hip_atomic_fetch_add(queues + x * (kLine / 2), step, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t head = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old), 0));
+      const uint32_t tail =
+          __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old >> 32), 0));
+      if (static_cast<uint64_t>(head) + tail < m) {
+        t = x + kQueues * (front ? head : m - 1u - tail);
+        break;
+      }
+      ++qi;
+    }
+    if (t == 0xFFFFFFFFu) break;
+    const WorkItem it = a.items[t];
+    if (front && it.key >= prio_key)
+      __builtin_amdgcn_s_setprio(3);
+    else
+      __builtin_amdgcn_s_setprio(0);
+    // the next message's index and metadata are loaded while this one hashes
+    uint32_t pos = it.begin + lane;
+    uint64_t i = 0, off = 0, len = 0;
+    int var = V;
+    if (pos < it.end) {
+      i = a.order[pos];
+      off = a.offs[i];
+      len = a.lens[i];
+      if constexpr (V == kMixed) var = a.vars[i];
+    }
+    while (pos < it.end) {
+      const uint32_t pn = pos + 64u;
+      uint64_t in = 0, offn = 0, lenn = 0;
+      int varn = V;
+      if (pn < it.end) {
+        in = a.order[pn];
+        offn = a.offs[in];
+        lenn = a.lens[in];
+        if constexpr (V == kMixed) varn = a.vars[in];
+      }
+      hash_one<V>(a.data, off, len, var, i, a.out, a.stride, row);
+      pos = pn;
+      i = in;
+      off = offn;
+      len = lenn;
+      var = varn;
+    }
+  }
+  __builtin_amdgcn_s_setprio(0);
+}
+
+__global__ void k_reset(uint32_t* __restrict__ meta, uint32_t words) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < words; k += gridDim.x * blockDim.x)
+    meta[k] = 0u;
 }
 
 // Count the dwords where two digest buffers differ (autotuner parity gate).
@@ -1035,22 +1204,24 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 struct Workspace {
-  uint32_t* meta = nullptr;  // hist | start | cursor | iend | ctl | sub-queues | simd flags
-  uint32_t* order = nullptr;
+  uint32_t* meta = nullptr;      // kMetaWords words (layout above), cleared at allocation
+  uint32_t* order = nullptr;     // bucketed order
   uint64_t order_cap = 0;
-  WorkItem* items = nullptr;
+  WorkItem* items = nullptr;     // queue items
   uint64_t items_cap = 0;
-  uint8_t* tree = nullptr;
+  uint32_t* deferred = nullptr;  // deferred chunk list
+  uint64_t deferred_cap = 0;
+  uint8_t* tree = nullptr;       // tree node buffer
   uint64_t tree_cap = 0;
-  uint32_t* host_hist = nullptr;  // pinned, for the per-bucket form
+  uint32_t* host_fold = nullptr;  // pinned: bucket sizes and starts, for the per-bucket form
 };
 
-constexpr uint32_t kMetaWords = kPartialsOff + kCopies * kPartialWords;
-
-// Measurement hook state (keccak_timing_*): event pairs around kernel launches.
+// Measurement hook state (keccak_timing_*): event pairs around kernel
+// launches, each tagged with the kind of kernel it brackets.
 struct Timing {
   bool on = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  std::vector<int> kind;
   size_t used = 0;
 };
 std::mutex g_tmu;
@@ -1060,7 +1231,7 @@ Timing g_timing;
 struct TimedLaunch {
   hipEvent_t stop = nullptr;
   hipStream_t s;
-  explicit TimedLaunch(hipStream_t st) : s(st) {
+  TimedLaunch(hipStream_t st, int kind) : s(st) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing.on) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1072,7 +1243,9 @@ struct TimedLaunch {
         return;
       }
       g_timing.pool.push_back(e);
+      g_timing.kind.push_back(kind);
     }
+    g_timing.kind[g_timing.used] = kind;
     auto& e = g_timing.pool[g_timing.used++];
     (void)hipEventRecord(e.first, s);
     stop = e.second;
@@ -1119,9 +1292,27 @@ int grow(void** ptr, uint64_t* cap, uint64_t need, hipStream_t stream) {
   return KB_OK;
 }
 
-// Queue items of a batch of n messages: ceil(n / 64) in arrival order, or at
-// most one partial item per bucket more than that when bucketed.
+// Queue items of a batch of n messages: at most ceil(n / 64) whole ones and
+// one partial item per bucket.
 uint64_t max_items(uint64_t n) { return n / 64 + kKeyBins + 1; }
+
+// Clear a freshly allocated metadata area with a kernel on the stream (not
+// a memset: the call may be recorded into a graph).
+int clear_meta(uint32_t* meta, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(64), dim3(256), 0, s, meta, static_cast<uint32_t>(kMetaWords));
+  KB_HIP(hipGetLastError());
+  return KB_OK;
+}
+
+// Size the batch part of a workspace for `msgs` messages.
+int grow_batch(Workspace& w, uint64_t msgs, hipStream_t stream) {
+  int rc = grow(reinterpret_cast<void**>(&w.order), &w.order_cap, msgs * 4ull, stream);
+  if (!rc)
+    rc = grow(reinterpret_cast<void**>(&w.items), &w.items_cap, max_items(msgs) * sizeof(WorkItem),
+              stream);
+  if (!rc) rc = grow(reinterpret_cast<void**>(&w.deferred), &w.deferred_cap, (msgs + 63) / 64 * 4ull, stream);
+  return rc;
+}
 
 int get_ws(hipStream_t stream, uint64_t msgs, uint64_t tree_bytes, Workspace** out) {
   int dev = 0;
@@ -1131,13 +1322,11 @@ int get_ws(hipStream_t stream, uint64_t msgs, uint64_t tree_bytes, Workspace** o
   if (!w.meta) {
     uint64_t cap = 0;
     int rc = grow(reinterpret_cast<void**>(&w.meta), &cap, kMetaWords * 4ull, stream);
+    if (!rc) rc = clear_meta(w.meta, stream);
     if (rc) return rc;
   }
   if (msgs) {
-    int rc = grow(reinterpret_cast<void**>(&w.order), &w.order_cap, msgs * 4ull, stream);
-    if (rc) return rc;
-    const uint64_t items = max_items(msgs);
-    rc = grow(reinterpret_cast<void**>(&w.items), &w.items_cap, items * sizeof(WorkItem), stream);
+    int rc = grow_batch(w, msgs, stream);
     if (rc) return rc;
   }
   if (tree_bytes) {
@@ -1170,7 +1359,7 @@ int launch_plain(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
   const uint64_t blocks = (count + kBlock - 1) / kBlock;
   if (blocks > 0x7FFFFFFFull) return fail(KB_EINVAL, "batch too large for one launch");
   {
-    TimedLaunch tl(s);
+    TimedLaunch tl(s, KB_KERNEL_PLAIN);
     hipLaunchKernelGGL(k_plain<V>, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s,
                        b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
   }
@@ -1190,7 +1379,7 @@ int launch_split(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
   uint64_t grid = (count + kSplitGroups - 1) / kSplitGroups;
   if (grid > static_cast<uint64_t>(16 * cus)) grid = 16 * cus;
   {
-    TimedLaunch tl(s);
+    TimedLaunch tl(s, KB_KERNEL_SPLIT);
     hipLaunchKernelGGL(k_split<V>, dim3(static_cast<uint32_t>(grid)), dim3(kSplitBlock), 0, s,
                        b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
   }
@@ -1198,108 +1387,103 @@ int launch_split(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
   return KB_OK;
 }
 
+// Workgroups of `kernel` that fit on the chip at once, capped by the tile's
+// waves per SIMD (a 256-thread workgroup is one wave on each of a CU's four
+// SIMDs).
+int resident_grid(const void* kernel, const kb_tile* tile, int cus, uint32_t* grid) {
+  int per_cu = 0;
+  KB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
+  if (per_cu < 1) per_cu = 1;
+  if (tile && tile->waves_per_simd > 0 && tile->waves_per_simd < per_cu) per_cu = tile->waves_per_simd;
+  *grid = static_cast<uint32_t>(per_cu * cus);
+  return KB_OK;
+}
+
+// The persistent form (two passes) or, with mode KB_MODE_PER_BUCKET, the
+// same passes without hashing followed by one plain launch per bucket, the
+// bucket sizes read back on the host.
 template <int V>
-int run_schedule(const Batch& b, Workspace& w, uint32_t steps, int force_sort, uint64_t lanes,
-                 hipStream_t s) {
-  uint32_t* hist = w.meta;
-  uint32_t* start = w.meta + kKeyBins;
-  uint32_t* cursor = w.meta + 2 * kKeyBins;
-  uint32_t* iend = w.meta + 3 * kKeyBins;
-  uint32_t* ctl = w.meta + 4 * kKeyBins;
+int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hipStream_t s,
+                 const uint32_t* n_dev) {
+  const bool per_bucket = mode == KB_MODE_PER_BUCKET;
   int dev = 0, cus = 0;
   KB_HIP(hipGetDevice(&dev));
   int rc = cu_count(dev, &cus);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_reset, dim3(64), dim3(256), 0, s, w.meta, kMetaWords);
-  KB_HIP(hipGetLastError());
-  // about 2 passes of 4 waves x kCountUnroll 128-message pairs per workgroup,
-  // at most 2 workgroups per CU: the workgroups' closing atomics serialise per
-  // address, so fewer, longer workgroups finish sooner (on 2^24 lengths the
-  // whole schedule costs 48 us at 2 per CU, 54 at 4 and 65 at 8)
-  const uint64_t per_wg = 128ull * 4 * kCountUnroll * 2;
-  uint64_t cblocks = (b.n + per_wg - 1) / per_wg;
-  if (cblocks > static_cast<uint64_t>(2 * cus)) cblocks = 2 * cus;
-  hipLaunchKernelGGL(k_count<V>, dim3(static_cast<uint32_t>(cblocks)), dim3(kBlock), 0, s, b.lens,
-                     b.vars, b.n, hist, w.meta + kHistCopiesOff, w.meta + kPartialsOff);
-  KB_HIP(hipGetLastError());
+  uint32_t grid1 = 0, grid2 = 0;
+  rc = resident_grid(reinterpret_cast<const void*>(&k_first<V>), tile, cus, &grid1);
+  if (!rc) rc = resident_grid(reinterpret_cast<const void*>(&k_second<V>), tile, cus, &grid2);
+  if (rc) return rc;
+  PassArgs a{};
+  a.data = b.data;
+  a.offs = b.offs;
+  a.lens = b.lens;
+  a.vars = b.vars;
+  a.n = b.n;
+  a.out = b.out;
+  a.stride = b.stride;
+  a.meta = w.meta;
+  a.deferred = w.deferred;
+  a.order = w.order;
+  a.items = w.items;
+  a.steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 4u;
   // at most eight split messages per SIMD: one 8-group split item for each
   // SIMD's front wave (mixed-variant kernel only; the per-bucket form takes
   // none)
-  const uint32_t split_cap = V == kMixed && !force_sort ? 8u * 4u * static_cast<uint32_t>(cus) : 0u;
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kBlock), 0, s, hist, w.meta + kHistCopiesOff,
-                     w.meta + kPartialsOff, start, iend, ctl, b.n, steps, force_sort, split_cap,
-                     lanes);
+  a.split_cap = V == kMixed && !per_bucket ? 8u * 4u * static_cast<uint32_t>(cus) : 0u;
+  a.lanes = static_cast<uint64_t>(grid2) * kBlock;
+  a.hash = per_bucket ? 0 : 1;
+  a.n_dev = n_dev;
+  {
+    TimedLaunch tl(s, KB_KERNEL_FIRST_PASS);
+    hipLaunchKernelGGL(k_first<V>, dim3(grid1), dim3(kBlock), 0, s, a);
+  }
   KB_HIP(hipGetLastError());
-  const uint64_t iblocks = (max_items(b.n) + kBlock - 1) / kBlock;
-  const uint64_t sblocks = (b.n + kScatterTile - 1) / kScatterTile;
-  hipLaunchKernelGGL(k_fill<V>, dim3(static_cast<uint32_t>(iblocks + sblocks)), dim3(kBlock), 0, s,
-                     b.lens, b.vars, b.n, hist, start, cursor, iend, ctl, steps,
-                     static_cast<uint32_t>(iblocks), w.items, w.order);
+  {
+    TimedLaunch tl(s, KB_KERNEL_SECOND_PASS);
+    hipLaunchKernelGGL(k_second<V>, dim3(grid2), dim3(kBlock), 0, s, a);
+  }
   KB_HIP(hipGetLastError());
+  if (!per_bucket) return KB_OK;
+  if (!w.host_fold)
+    KB_HIP(hipHostMalloc(reinterpret_cast<void**>(&w.host_fold), 2 * kKeyBins * 4, 0));
+  static_assert(M_START == M_FOLD + kKeyBins, "bucket sizes and starts are adjacent");
+  KB_HIP(hipMemcpyAsync(w.host_fold, w.meta + M_FOLD, 2 * kKeyBins * 4, hipMemcpyDeviceToHost, s));
+  KB_HIP(hipStreamSynchronize(s));
+  for (int key = static_cast<int>(kKeyBins) - 1; key >= 1; --key) {
+    const uint32_t c = w.host_fold[key];
+    if (!c) continue;
+    rc = launch_plain<V>(b, w.order, w.host_fold[kKeyBins + key], c, s);
+    if (rc) return rc;
+  }
   return KB_OK;
 }
 
+// n_dev (persistent form only): the message count is read from that device
+// word when the kernels run, b.n being its upper bound.
 template <int V>
-int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Workspace* own) {
+int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Workspace* own,
+              const uint32_t* n_dev) {
   if (mode == KB_MODE_PLAIN) return launch_plain<V>(b, nullptr, 0, b.n, s);
   if (mode == KB_MODE_SPLIT) return launch_split<V>(b, nullptr, 0, b.n, s);
   if (b.n >= 0xFFFFFFFFull) return launch_plain<V>(b, nullptr, 0, b.n, s);  // 32-bit order[]
   Workspace* w = own;
   int rc = own ? KB_OK : get_ws(s, b.n, 0, &w);
   if (rc) return rc;
-  uint32_t steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 4u;
-  if (mode == KB_MODE_PER_BUCKET) {
-    rc = run_schedule<V>(b, *w, steps, 1, 0, s);
-    if (rc) return rc;
-    if (!w->host_hist) KB_HIP(hipHostMalloc(reinterpret_cast<void**>(&w->host_hist), kKeyBins * 4, 0));
-    KB_HIP(hipMemcpyAsync(w->host_hist, w->meta, kKeyBins * 4, hipMemcpyDeviceToHost, s));
-    KB_HIP(hipStreamSynchronize(s));
-    uint64_t first = 0;
-    for (int key = static_cast<int>(kKeyBins) - 1; key >= 1; --key) {
-      const uint32_t c = w->host_hist[key];
-      if (!c) continue;
-      rc = launch_plain<V>(b, w->order, first, c, s);
-      if (rc) return rc;
-      first += c;
-    }
-    return KB_OK;
-  }
-  int dev = 0, cus = 0;
-  KB_HIP(hipGetDevice(&dev));
-  rc = cu_count(dev, &cus);
-  if (rc) return rc;
-  int per_cu = 0;
-  KB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<V>, kBlock, 0));
-  if (per_cu < 1) per_cu = 1;
-  if (tile && tile->waves_per_simd > 0) {
-    const int want = tile->waves_per_simd * 4 / (kBlock / 64);
-    if (want >= 1 && want < per_cu) per_cu = want;
-  }
-  const uint32_t grid = static_cast<uint32_t>(per_cu * cus);
-  rc = run_schedule<V>(b, *w, steps, 0, static_cast<uint64_t>(grid) * kBlock, s);
-  if (rc) return rc;
-  {
-    TimedLaunch tl(s);
-    hipLaunchKernelGGL(k_persistent<V>, dim3(grid), dim3(kBlock), 0, s, b.data, b.offs, b.lens,
-                       b.vars, w->order, w->items, w->meta + 4 * kKeyBins,
-                       reinterpret_cast<unsigned long long*>(w->meta + 4 * kKeyBins + CTL_WORDS),
-                       w->meta + 4 * kKeyBins + CTL_WORDS + kQueueAreaDw, b.out,
-                       b.stride);
-  }
-  KB_HIP(hipGetLastError());
-  return KB_OK;
+  return run_two_pass<V>(b, *w, mode, tile, s, n_dev);
 }
 
 // `own`: a caller-owned workspace (a captured graph's), else the stream's.
-int dispatch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Workspace* own = nullptr) {
+int dispatch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Workspace* own = nullptr,
+             const uint32_t* n_dev = nullptr) {
   switch (b.variant) {
-    case 0: return run_batch<0>(b, mode, tile, s, own);
-    case 1: return run_batch<1>(b, mode, tile, s, own);
-    case 2: return run_batch<2>(b, mode, tile, s, own);
-    case 3: return run_batch<3>(b, mode, tile, s, own);
-    case kShake128: return run_batch<kShake128>(b, mode, tile, s, own);
-    case kShake256: return run_batch<kShake256>(b, mode, tile, s, own);
-    default: return run_batch<kMixed>(b, mode, tile, s, own);
+    case 0: return run_batch<0>(b, mode, tile, s, own, n_dev);
+    case 1: return run_batch<1>(b, mode, tile, s, own, n_dev);
+    case 2: return run_batch<2>(b, mode, tile, s, own, n_dev);
+    case 3: return run_batch<3>(b, mode, tile, s, own, n_dev);
+    case kShake128: return run_batch<kShake128>(b, mode, tile, s, own, n_dev);
+    case kShake256: return run_batch<kShake256>(b, mode, tile, s, own, n_dev);
+    default: return run_batch<kMixed>(b, mode, tile, s, own, n_dev);
   }
 }
 
@@ -1383,7 +1567,7 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
       const int levels = L - first < cap ? L - first : cap;
       const uint64_t blocks = (lv.m[first] + kBlock - 1) / kBlock;
       {
-        TimedLaunch tl(s);
+        TimedLaunch tl(s, KB_KERNEL_TREE);
         if (w8 || first > 0)
           hipLaunchKernelGGL((k_tree<V, kBlock, kb::kPrefetch<V>, true>),
                              dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data, total,
@@ -1397,7 +1581,7 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
       first += levels;
     } else {
       {
-        TimedLaunch tl(s);
+        TimedLaunch tl(s, KB_KERNEL_TREE);
         hipLaunchKernelGGL((k_tree<V, kTreeTopThreads, false, true, kTreeTop>), dim3(1),
                            dim3(kTreeTopThreads), 0, s, data, total, leaf, w->tree, root, first,
                            L - first, L, lv);
@@ -1433,18 +1617,19 @@ void free_ws(Workspace& w) {
   if (w.meta) (void)hipFree(w.meta);
   if (w.order) (void)hipFree(w.order);
   if (w.items) (void)hipFree(w.items);
+  if (w.deferred) (void)hipFree(w.deferred);
   if (w.tree) (void)hipFree(w.tree);
-  if (w.host_hist) (void)hipHostFree(w.host_hist);
+  if (w.host_fold) (void)hipHostFree(w.host_fold);
   w = Workspace{};
 }
 
-// Size a graph's private workspace for `msgs` messages and `tree_bytes`.
+// Size a graph's private workspace for `msgs` messages and `tree_bytes`
+// (cleared on the stream before the capture starts).
 int size_ws(Workspace& w, uint64_t msgs, uint64_t tree_bytes, hipStream_t s) {
   uint64_t cap = 0;
   int rc = grow(reinterpret_cast<void**>(&w.meta), &cap, kMetaWords * 4ull, s);
-  if (!rc && msgs) rc = grow(reinterpret_cast<void**>(&w.order), &w.order_cap, msgs * 4ull, s);
-  if (!rc && msgs)
-    rc = grow(reinterpret_cast<void**>(&w.items), &w.items_cap, max_items(msgs) * sizeof(WorkItem), s);
+  if (!rc) rc = clear_meta(w.meta, s);
+  if (!rc && msgs) rc = grow_batch(w, msgs, s);
   if (!rc && tree_bytes) rc = grow(reinterpret_cast<void**>(&w.tree), &w.tree_cap, tree_bytes, s);
   return rc;
 }
@@ -1495,11 +1680,60 @@ int capture(hipStream_t stream, F&& enqueue, kb_graph* g, kb_graph** out) {
 
 }  // namespace
 
+// The allocation-free entry point's workspace: one static array per device,
+// laid out as a Workspace for at most KB_NOALLOC_MAX_MSGS messages.
+namespace {
+constexpr uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t{255}; }
+constexpr uint64_t kNoAllocMax = KB_NOALLOC_MAX_MSGS;
+constexpr uint64_t kScratchOrderOff = align256(uint64_t{kMetaWords} * 4u);
+constexpr uint64_t kScratchItemsOff = kScratchOrderOff + align256(kNoAllocMax * 4u);
+constexpr uint64_t kScratchDeferredOff =
+    kScratchItemsOff + align256((kNoAllocMax / 64 + kKeyBins + 1) * sizeof(WorkItem));
+constexpr uint64_t kScratchBytes = kScratchDeferredOff + align256((kNoAllocMax + 63) / 64 * 4u);
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch;  // device -> the array's address on that device
+
+// The static workspace of the current device.  On the first call on a
+// device its address is looked up (host code must not use the array's name:
+// that is a host-side stand-in) and its metadata cleared on `stream`.
+int scratch_ws(hipStream_t stream, Workspace* w) {
+  int dev = 0;
+  KB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(KB_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    const int rc = clear_meta(static_cast<uint32_t*>(p), stream);
+    if (rc) return rc;
+    it = g_scratch.emplace(dev, static_cast<uint8_t*>(p)).first;
+  }
+  uint8_t* base = it->second;
+  *w = Workspace{};
+  w->meta = reinterpret_cast<uint32_t*>(base);
+  w->order = reinterpret_cast<uint32_t*>(base + kScratchOrderOff);
+  w->order_cap = kNoAllocMax * 4u;
+  w->items = reinterpret_cast<WorkItem*>(base + kScratchItemsOff);
+  w->items_cap = (kNoAllocMax / 64 + kKeyBins + 1) * sizeof(WorkItem);
+  w->deferred = reinterpret_cast<uint32_t*>(base + kScratchDeferredOff);
+  w->deferred_cap = (kNoAllocMax + 63) / 64 * 4u;
+  return KB_OK;
+}
+}  // namespace
+
 namespace kb {
 int set_last_error(int code, const char* msg) {
   g_err = msg ? msg : "";
   return code;
 }
+hipGraph_t native_graph(kb_graph* g) { return g ? g->h.graph : nullptr; }
 }  // namespace kb
 
 extern "C" {
@@ -1512,6 +1746,24 @@ int keccak_batch(int variant, const uint8_t* d_data, const uint64_t* d_offsets,
   }
   return batch_entry(variant, nullptr, d_data, d_offsets, d_lengths, n, d_digests,
                      KB_MODE_PERSISTENT, nullptr, stream);
+}
+
+int keccak_batch_noalloc(int variant, const uint8_t* d_data, const uint64_t* d_offsets,
+                         const uint64_t* d_lengths, uint64_t n, uint8_t* d_digests,
+                         hipStream_t stream) {
+  g_err.clear();
+  if (variant < 0 || variant > 3)
+    return fail(KB_EINVAL, "variant %d is not a SHA-3 variant (0..3)", variant);
+  Batch b{variant, nullptr, d_data, d_offsets, d_lengths, n, d_digests, out_stride(variant)};
+  int rc = check_batch(b, KB_MODE_PERSISTENT);
+  if (rc || n == 0) return rc;
+  if (n > kNoAllocMax)
+    return fail(KB_EINVAL, "n = %llu is more than the %llu messages the static workspace holds",
+                static_cast<unsigned long long>(n), static_cast<unsigned long long>(kNoAllocMax));
+  Workspace w;
+  rc = scratch_ws(stream, &w);
+  if (rc) return rc;
+  return dispatch(b, KB_MODE_PERSISTENT, nullptr, stream, &w);
 }
 
 int keccak_batch_xof(int security, const uint8_t* d_data, const uint64_t* d_offsets,
@@ -1706,6 +1958,34 @@ int keccak_graph_create(int variant, const uint8_t* d_variants, const uint8_t* d
                  g, out);
 }
 
+int keccak_graph_create_counted(int variant, const uint8_t* d_variants, const uint8_t* d_data,
+                                const uint64_t* d_offsets, const uint64_t* d_lengths,
+                                const uint32_t* d_count, uint64_t max_n, uint8_t* d_digests,
+                                hipStream_t stream, kb_graph** out) {
+  g_err.clear();
+  if (!out) return fail(KB_EINVAL, "NULL output pointer");
+  if (variant != -1 && (variant < 0 || variant > 3))
+    return fail(KB_EINVAL, "variant %d is neither -1 (mixed) nor a SHA-3 variant", variant);
+  if (!d_count) return fail(KB_EINVAL, "NULL count pointer");
+  if (max_n == 0 || max_n >= 0xFFFFFFFFull) return fail(KB_EINVAL, "max_n must be in [1, 2^32 - 1)");
+  const int v = variant == -1 ? kMixed : variant;
+  Batch b{v, d_variants, d_data, d_offsets, d_lengths, max_n, d_digests, out_stride(v)};
+  int rc = check_batch(b, KB_MODE_PERSISTENT);
+  if (rc) return rc;
+  kb_graph* g = new kb_graph();
+  int dev = 0, cus = 0;
+  rc = hipGetDevice(&dev) == hipSuccess ? cu_count(dev, &cus) : fail(KB_EHIP, "hipGetDevice failed");
+  if (!rc) rc = size_ws(g->ws, max_n, 0, stream);
+  if (rc) {
+    free_ws(g->ws);
+    delete g;
+    return rc;
+  }
+  return capture(stream,
+                 [&](hipStream_t cs) { return dispatch(b, KB_MODE_PERSISTENT, nullptr, cs, &g->ws, d_count); },
+                 g, out);
+}
+
 int keccak_graph_create_merkle(int variant, const uint8_t* d_data, uint64_t total_len,
                                uint64_t leaf_size, uint8_t* d_root, hipStream_t stream,
                                kb_graph** out) {
@@ -1778,11 +2058,7 @@ int keccak_release(void) {
     int prev = -1;
     if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(kv.first.first) == hipSuccess) {
       if (hipDeviceSynchronize() != hipSuccess) rc = KB_EHIP;
-      if (w.meta) (void)hipFree(w.meta);
-      if (w.order) (void)hipFree(w.order);
-      if (w.items) (void)hipFree(w.items);
-      if (w.tree) (void)hipFree(w.tree);
-      if (w.host_hist) (void)hipHostFree(w.host_hist);
+      free_ws(w);
       (void)hipSetDevice(prev);
     } else {
       rc = KB_EHIP;
@@ -1801,21 +2077,37 @@ int keccak_timing_enable(int on) {
   return KB_OK;
 }
 
-int keccak_timing_read(double* total_ms, uint64_t* launches) {
+// Sum of the bracketed durations of kernels of kind `kind` (-1: every kind).
+int timing_sum(int kind, double* total_ms, uint64_t* launches) {
   g_err.clear();
   if (!total_ms || !launches) return fail(KB_EINVAL, "NULL output pointer");
   std::lock_guard<std::mutex> lk(g_tmu);
   double sum = 0.0;
+  uint64_t cnt = 0;
   for (size_t k = 0; k < g_timing.used; ++k) {
+    if (kind >= 0 && g_timing.kind[k] != kind) continue;
     auto& e = g_timing.pool[k];
     KB_HIP(hipEventSynchronize(e.second));
     float ms = 0.f;
     KB_HIP(hipEventElapsedTime(&ms, e.first, e.second));
     sum += ms;
+    ++cnt;
   }
   *total_ms = sum;
-  *launches = g_timing.used;
+  *launches = cnt;
   return KB_OK;
+}
+
+int keccak_timing_read(double* total_ms, uint64_t* launches) {
+  return timing_sum(-1, total_ms, launches);
+}
+
+int keccak_timing_read_kernel(int kind, double* total_ms, uint64_t* launches) {
+  if (kind < KB_KERNEL_FIRST_PASS || kind > KB_KERNEL_TREE) {
+    g_err.clear();
+    return fail(KB_EINVAL, "unknown kernel kind %d", kind);
+  }
+  return timing_sum(kind, total_ms, launches);
 }
 
 const char* keccak_last_error(void) { return g_err.c_str(); }

@@ -15,7 +15,7 @@
 // For b = 25, 50 and 100 the unused high bits of the last byte are cleared.
 #include <hip/hip_runtime.h>
 
-#include "kb_error.h"
+#include "kb_internal.h"
 #include "kbatch.h"
 #include "keccak_device.h"
 

@@ -3,17 +3,22 @@
 // Requests (a variant and a list of (offset, length) slices of a
 // device-resident byte pool) are queued by any host thread.  One worker
 // thread forms steps: it admits queued requests in arrival order while the
-// step has message slots left (a request never straddles steps; one larger
-// than a step is rejected at submit), writes the step's descriptors into a
-// pinned host buffer, and enqueues on one of `steps_in_flight` HIP streams:
-// the descriptor upload, one keccak_batch_mixed over the whole step, and the
-// digest download into pinned memory.  Up to `steps_in_flight` steps are in
-// flight at once, so requests that arrive while others are on the GPU are admitted into
-// the next step as soon as a step slot (device buffers) frees up, and their
-// work overlaps the running step on the device.  When a step's event has
-// completed the worker copies each request's digests out and marks it done.
+// step has message slots and byte budget left (a request never straddles
+// steps; one larger than a step is rejected at submit), writes the step's
+// descriptors into pinned host buffers and replays the step slot's graph on
+// the slot's stream.  The graph, captured when the server is created, holds
+// the uploads of the descriptors and of the message count, both passes of
+// the mixed-variant persistent form (which read the count from device
+// memory, so one capture serves every step size) and the digest download;
+// the copy sizes are set to the step's message count before each replay.
+// Up to `steps_in_flight` steps are in flight at once, so requests that
+// arrive while others are on the GPU are admitted into the next step as
+// soon as a step slot frees up, and their work overlaps the running steps on
+// the device.  When a step's event has completed the worker copies each
+// request's digests out and marks it done.
 //
-// The executor is pluggable: the default one does the above with HIP; a
+// The executor is pluggable: the default one does the above with HIP (or,
+// with KB_SERVER_EAGER, as separate copies and a keccak_batch_mixed call); a
 // caller-supplied callback replaces upload/launch/download (used to test the
 // admission and completion logic without a GPU).
 #include <hip/hip_runtime.h>
@@ -29,6 +34,7 @@
 #include <thread>
 #include <vector>
 
+#include "kb_internal.h"
 #include "kbatch.h"
 
 namespace {
@@ -39,6 +45,7 @@ struct Request {
   uint64_t id;
   int variant;
   std::vector<uint64_t> offs, lens;
+  uint64_t bytes = 0;  // sum of the lengths
   Clock::time_point t_submit;
   Clock::time_point t_done;
   std::vector<uint8_t> digests;  // n * 64
@@ -56,8 +63,16 @@ struct StepSlot {
   uint64_t* d_lens = nullptr;
   uint8_t* d_vars = nullptr;
   uint8_t* d_out = nullptr;
+  uint32_t* h_count = nullptr;  // pinned: the step's message count
+  uint32_t* d_count = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  // the step graph: count and descriptor uploads -> the batch -> download
+  kb_graph* batch = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t n_count = nullptr, n_offs = nullptr, n_lens = nullptr, n_vars = nullptr,
+                 n_batch = nullptr, n_out = nullptr;
   bool busy = false;
   uint64_t n = 0;
   std::vector<Request*> reqs;
@@ -112,6 +127,19 @@ bool launch_step(kb_server* s, StepSlot& st) {
       return false;
     }
     return true;
+  }
+  if (st.exec) {
+    *st.h_count = static_cast<uint32_t>(n);
+    return hip_ok(hipGraphExecMemcpyNodeSetParams1D(st.exec, st.n_offs, st.d_offs, st.h_offs, n * 8,
+                                                    hipMemcpyHostToDevice), s, "step offsets size") &&
+           hip_ok(hipGraphExecMemcpyNodeSetParams1D(st.exec, st.n_lens, st.d_lens, st.h_lens, n * 8,
+                                                    hipMemcpyHostToDevice), s, "step lengths size") &&
+           hip_ok(hipGraphExecMemcpyNodeSetParams1D(st.exec, st.n_vars, st.d_vars, st.h_vars, n,
+                                                    hipMemcpyHostToDevice), s, "step variants size") &&
+           hip_ok(hipGraphExecMemcpyNodeSetParams1D(st.exec, st.n_out, st.h_out, st.d_out, n * 64,
+                                                    hipMemcpyDeviceToHost), s, "step digests size") &&
+           hip_ok(hipGraphLaunch(st.exec, st.stream), s, "step graph launch") &&
+           hip_ok(hipEventRecord(st.done, st.stream), s, "record event");
   }
   if (!hip_ok(hipMemcpyAsync(st.d_offs, st.h_offs, n * 8, hipMemcpyHostToDevice, st.stream), s, "upload offsets") ||
       !hip_ok(hipMemcpyAsync(st.d_lens, st.h_lens, n * 8, hipMemcpyHostToDevice, st.stream), s, "upload lengths") ||
@@ -178,11 +206,15 @@ void worker_main(kb_server* s) {
       std::unique_lock<std::mutex> lk(s->mu);
       if (s->stop && s->pending.empty() && !any_busy) return;
       if (free_slot) {
-        // admit in arrival order while the step has message slots left
+        // admit in arrival order while the step has message slots and
+        // byte budget left
+        uint64_t bytes = 0;
         while (!s->pending.empty()) {
           Request* r = s->pending.front();
           if (n + r->offs.size() > s->cfg.max_step_msgs) break;
+          if (s->cfg.max_step_bytes && bytes + r->bytes > s->cfg.max_step_bytes) break;
           n += r->offs.size();
+          bytes += r->bytes;
           batch.push_back(r);
           s->pending.pop_front();
         }
@@ -217,8 +249,7 @@ void worker_main(kb_server* s) {
       }
       ++s->steps;
       s->msgs += n;
-      for (Request* r : st.reqs)
-        for (uint64_t L : r->lens) s->bytes += L;
+      for (Request* r : st.reqs) s->bytes += r->bytes;
       if (n > s->max_step_msgs_seen) s->max_step_msgs_seen = n;
     }
     if (!launch_step(s, st)) {
@@ -226,6 +257,33 @@ void worker_main(kb_server* s) {
       complete_step(s, st);
     }
   }
+}
+
+// Build a slot's step graph: the count and descriptor uploads, then the
+// batch captured over the slot's buffers (count read on the device), then the
+// digest download.  The copy sizes are placeholders, set before each replay.
+bool build_step_graph(kb_server* s, StepSlot& st) {
+  const uint64_t m = s->cfg.max_step_msgs;
+  if (keccak_graph_create_counted(-1, st.d_vars, s->cfg.d_pool, st.d_offs, st.d_lens, st.d_count, m,
+                                  st.d_out, st.stream, &st.batch) != KB_OK)
+    return false;
+  if (hipGraphCreate(&st.graph, 0) != hipSuccess) return false;
+  if (hipGraphAddMemcpyNode1D(&st.n_count, st.graph, nullptr, 0, st.d_count, st.h_count, 4,
+                              hipMemcpyHostToDevice) != hipSuccess ||
+      hipGraphAddMemcpyNode1D(&st.n_offs, st.graph, nullptr, 0, st.d_offs, st.h_offs, 8,
+                              hipMemcpyHostToDevice) != hipSuccess ||
+      hipGraphAddMemcpyNode1D(&st.n_lens, st.graph, nullptr, 0, st.d_lens, st.h_lens, 8,
+                              hipMemcpyHostToDevice) != hipSuccess ||
+      hipGraphAddMemcpyNode1D(&st.n_vars, st.graph, nullptr, 0, st.d_vars, st.h_vars, 1,
+                              hipMemcpyHostToDevice) != hipSuccess)
+    return false;
+  const hipGraphNode_t uploads[4] = {st.n_count, st.n_offs, st.n_lens, st.n_vars};
+  if (hipGraphAddChildGraphNode(&st.n_batch, st.graph, uploads, 4, kb::native_graph(st.batch)) !=
+          hipSuccess ||
+      hipGraphAddMemcpyNode1D(&st.n_out, st.graph, &st.n_batch, 1, st.h_out, st.d_out, 64,
+                              hipMemcpyDeviceToHost) != hipSuccess)
+    return false;
+  return hipGraphInstantiate(&st.exec, st.graph, nullptr, nullptr, 0) == hipSuccess;
 }
 
 void free_slots(kb_server* s) {
@@ -244,6 +302,11 @@ void free_slots(kb_server* s) {
       if (st.d_lens) (void)hipFree(st.d_lens);
       if (st.d_vars) (void)hipFree(st.d_vars);
       if (st.d_out) (void)hipFree(st.d_out);
+      if (st.h_count) (void)hipHostFree(st.h_count);
+      if (st.d_count) (void)hipFree(st.d_count);
+      if (st.exec) (void)hipGraphExecDestroy(st.exec);
+      if (st.graph) (void)hipGraphDestroy(st.graph);
+      if (st.batch) (void)keccak_graph_destroy(st.batch);
       if (st.done) (void)hipEventDestroy(st.done);
       if (st.stream) (void)hipStreamDestroy(st.stream);
     }
@@ -262,6 +325,7 @@ int keccak_server_create(const kb_server_config* cfg, kb_server** out) {
     return srv_fail(KB_EINVAL, "max_step_msgs must be in [1, 2^32)");
   if (cfg->steps_in_flight < 1 || cfg->steps_in_flight > 8)
     return srv_fail(KB_EINVAL, "steps_in_flight must be 1..8");
+  if (cfg->flags & ~static_cast<uint32_t>(KB_SERVER_EAGER)) return srv_fail(KB_EINVAL, "unknown flags");
   if (!cfg->executor && !cfg->d_pool && cfg->pool_bytes)
     return srv_fail(KB_EINVAL, "d_pool is NULL");
   kb_server* s = new kb_server();
@@ -282,8 +346,12 @@ int keccak_server_create(const kb_server_config* cfg, kb_server** out) {
            hipMalloc(reinterpret_cast<void**>(&st.d_vars), m) == hipSuccess &&
            hipMalloc(reinterpret_cast<void**>(&st.d_out), m * 64) == hipSuccess &&
            hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess &&
-           keccak_reserve(m, 0, st.stream) == KB_OK;
+           hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess;
+      if (ok && (cfg->flags & KB_SERVER_EAGER)) ok = keccak_reserve(m, 0, st.stream) == KB_OK;
+      if (ok && !(cfg->flags & KB_SERVER_EAGER))
+        ok = hipHostMalloc(reinterpret_cast<void**>(&st.h_count), 4, 0) == hipSuccess &&
+             hipMalloc(reinterpret_cast<void**>(&st.d_count), 4) == hipSuccess &&
+             build_step_graph(s, st);
     }
   } else {
     for (StepSlot& st : s->slots) {
@@ -315,11 +383,20 @@ int keccak_server_submit(kb_server* s, int variant, const uint64_t* h_offsets,
     ++s->rejected;
     return srv_fail(KB_ENOMEM, "request has more messages than a step holds");
   }
-  for (uint64_t i = 0; i < n; ++i)
+  uint64_t bytes = 0;
+  for (uint64_t i = 0; i < n; ++i) {
     if (h_offsets[i] > s->cfg.pool_bytes || h_lengths[i] > s->cfg.pool_bytes - h_offsets[i])
       return srv_fail(KB_EINVAL, "a message lies outside the pool");
+    bytes += h_lengths[i];
+  }
+  if (s->cfg.max_step_bytes && bytes > s->cfg.max_step_bytes) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    ++s->rejected;
+    return srv_fail(KB_ENOMEM, "request has more message bytes than a step holds");
+  }
   Request* r = new Request();
   r->variant = variant;
+  r->bytes = bytes;
   r->offs.assign(h_offsets, h_offsets + n);
   r->lens.assign(h_lengths, h_lengths + n);
   r->t_submit = Clock::now();

@@ -25,17 +25,18 @@ MODE_PERSISTENT, MODE_PLAIN, MODE_PER_BUCKET, MODE_SPLIT = 0, 1, 2, 3
 MODES = {"persistent": 0, "plain": 1, "per_bucket": 2, "split": 3}
 
 KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
+NOALLOC_MAX_MSGS = 1 << 20
 
 # the C ABI entry points, in include/kbatch.h order
 EXPORTS = (
-    "keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_xof_ex",
-    "keccak_batch_ex", "merkle_root",
-    "keccak_autotune", "keccak_graph_create", "keccak_graph_create_merkle",
-    "keccak_graph_launch", "keccak_graph_destroy",
-    "keccak_server_create", "keccak_server_submit", "keccak_server_poll", "keccak_server_result",
-    "keccak_server_stats", "keccak_server_destroy", "keccak_server_last_error",
-    "keccak_tree_workspace_bytes", "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve",
-    "keccak_release", "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu", "keccak_probe_perm",
+    "keccak_batch", "keccak_batch_noalloc", "keccak_batch_mixed", "keccak_batch_xof",
+    "keccak_batch_xof_ex", "keccak_batch_ex", "merkle_root", "keccak_autotune",
+    "keccak_graph_create", "keccak_graph_create_counted", "keccak_graph_create_merkle", "keccak_graph_launch",
+    "keccak_graph_destroy", "keccak_server_create", "keccak_server_submit", "keccak_server_poll",
+    "keccak_server_result", "keccak_server_stats", "keccak_server_destroy",
+    "keccak_server_last_error", "keccak_tree_workspace_bytes", "keccak_digest_bytes",
+    "keccak_rate_bytes", "keccak_reserve", "keccak_release", "keccak_timing_enable",
+    "keccak_timing_read", "keccak_timing_read_kernel", "keccak_probe_valu", "keccak_probe_perm",
     "keccak_probe_copy", "keccak_last_error", "keccak_version", "keccak_p_batch",
 )
 
@@ -56,11 +57,14 @@ EXECUTOR = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes
                             ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint8))
 
 
+SERVER_EAGER = 1
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("d_pool", ctypes.c_void_p), ("pool_bytes", ctypes.c_uint64),
                 ("max_step_msgs", ctypes.c_uint64), ("steps_in_flight", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("executor", EXECUTOR),
-                ("executor_user", ctypes.c_void_p)]
+                ("flags", ctypes.c_uint32), ("executor", EXECUTOR),
+                ("executor_user", ctypes.c_void_p), ("max_step_bytes", ctypes.c_uint64)]
 
 
 class ServerStats(ctypes.Structure):
@@ -85,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     lib.keccak_batch.argtypes = [i32, vp, vp, vp, u64, vp, vp]
+    lib.keccak_batch_noalloc.argtypes = [i32, vp, vp, vp, u64, vp, vp]
     lib.keccak_batch_mixed.argtypes = [vp, vp, vp, vp, u64, vp, vp]
     lib.keccak_batch_ex.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile), vp]
     lib.keccak_batch_xof.argtypes = [i32, vp, vp, vp, u64, u64, vp, vp]
@@ -100,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_timing_enable.argtypes = [i32]
     lib.keccak_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_uint64)]
+    lib.keccak_timing_read_kernel.argtypes = [i32, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_uint64)]
     lib.keccak_probe_valu.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), vp]
     lib.keccak_probe_perm.argtypes = [ctypes.c_uint32, i32, ctypes.POINTER(ctypes.c_double),
@@ -111,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     pp = ctypes.POINTER(ctypes.c_void_p)
     lib.keccak_graph_create.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile),
                                         vp, pp]
+    lib.keccak_graph_create_counted.argtypes = [i32, vp, vp, vp, vp, vp, u64, vp, vp, pp]
     lib.keccak_graph_create_merkle.argtypes = [i32, vp, u64, u64, vp, vp, pp]
     lib.keccak_graph_launch.argtypes = [vp, vp]
     lib.keccak_graph_destroy.argtypes = [vp]
@@ -126,13 +134,15 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_last_error.restype = ctypes.c_char_p
     lib.keccak_version.argtypes = []
     lib.keccak_version.restype = ctypes.c_char_p
-    for f in ("keccak_batch", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_xof_ex",
+    for f in ("keccak_batch", "keccak_batch_noalloc", "keccak_batch_mixed", "keccak_batch_xof", "keccak_batch_xof_ex",
               "keccak_batch_ex",
               "merkle_root",
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
-              "keccak_timing_enable", "keccak_timing_read", "keccak_probe_valu",
+              "keccak_timing_enable", "keccak_timing_read", "keccak_timing_read_kernel",
+              "keccak_probe_valu",
               "keccak_probe_perm", "keccak_probe_copy", "keccak_autotune", "keccak_graph_create",
-              "keccak_graph_create_merkle", "keccak_graph_launch", "keccak_graph_destroy",
+              "keccak_graph_create_counted", "keccak_graph_create_merkle", "keccak_graph_launch",
+              "keccak_graph_destroy",
               "keccak_server_create", "keccak_server_submit", "keccak_server_poll",
               "keccak_server_result", "keccak_server_stats", "keccak_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
@@ -224,6 +234,34 @@ def keccak_batch(variant, data: torch.Tensor, offsets: torch.Tensor, lengths: to
                                  ctypes.byref(tile) if tile is not None else None,
                                  _stream_handle(stream))
     _check(rc)
+    return out
+
+
+def keccak_batch_noalloc(variant, data: torch.Tensor, offsets: torch.Tensor,
+                         lengths: torch.Tensor, out: torch.Tensor, stream=None,
+                         check_bounds: bool = True) -> torch.Tensor:
+    """keccak_batch through the entry point that allocates nothing (a static
+    per-device workspace for up to NOALLOC_MAX_MSGS messages, shared by every
+    call on the device: calls must not overlap).  `out` (uint8[n, D]) is
+    required, since allocating it would defeat the purpose."""
+    _require_gpu()
+    lib = load_library()
+    v = variant_id(variant)
+    n = offsets.numel()
+    if data.dtype != torch.uint8 or not data.is_cuda or not data.is_contiguous():
+        raise TypeError("data must be a contiguous uint8 device tensor")
+    if not offsets.is_contiguous() or not lengths.is_contiguous():
+        raise ValueError("offsets and lengths must be contiguous")
+    offsets = _as_u64_view(offsets, "offsets")
+    lengths = _as_u64_view(lengths, "lengths", n)
+    if check_bounds:
+        _check_bounds(data, offsets, lengths)
+    D = DIGEST_BYTES[v]
+    if out.dtype != torch.uint8 or out.numel() != n * D or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous uint8 tensor of {n * D} bytes")
+    dptr = _ptr(data) if data.numel() else ctypes.c_void_p(out.data_ptr())
+    _check(lib.keccak_batch_noalloc(v, dptr, _ptr(offsets), _ptr(lengths), n, _ptr(out),
+                                    _stream_handle(stream)))
     return out
 
 
@@ -400,6 +438,27 @@ def graph_batch(variant, data, offsets, lengths, out, variants=None, mode="persi
     return Graph(h, (data, offsets, lengths, out, variants))
 
 
+def graph_counted(variant, data, offsets, lengths, count, out, variants=None,
+                  stream=None) -> Graph:
+    """Capture the persistent form over up to offsets.numel() messages whose
+    count is read, each replay, from `count` (a one-element uint32/int32
+    device tensor)."""
+    _require_gpu()
+    lib = load_library()
+    v = -1 if variant == -1 else variant_id(variant)
+    n = offsets.numel()
+    offsets = _as_u64_view(offsets, "offsets")
+    lengths = _as_u64_view(lengths, "lengths", n)
+    _check_bounds(data, offsets, lengths)
+    if count.numel() != 1 or count.element_size() != 4 or not count.is_cuda:
+        raise TypeError("count must be a one-element 32-bit device tensor")
+    h = ctypes.c_void_p(0)
+    _check(lib.keccak_graph_create_counted(v, _ptr(variants), _ptr(data), _ptr(offsets),
+                                           _ptr(lengths), _ptr(count), n, _ptr(out),
+                                           _stream_handle(stream), ctypes.byref(h)))
+    return Graph(h, (data, offsets, lengths, count, out, variants))
+
+
 def graph_merkle(variant, data, leaf_size: int, out, stream=None) -> Graph:
     _require_gpu()
     lib = load_library()
@@ -417,7 +476,8 @@ class Server:
     runs without a GPU."""
 
     def __init__(self, pool: torch.Tensor | None, max_step_msgs: int = 1 << 16,
-                 steps_in_flight: int = 2, executor=None, pool_bytes: int | None = None):
+                 steps_in_flight: int = 2, executor=None, pool_bytes: int | None = None,
+                 max_step_bytes: int = 0, graphs: bool = True):
         import numpy as np
         lib = load_library()
         self._np = np
@@ -450,6 +510,8 @@ class Server:
             cfg.executor = self._cb
         cfg.max_step_msgs = int(max_step_msgs)
         cfg.steps_in_flight = int(steps_in_flight)
+        cfg.max_step_bytes = int(max_step_bytes)
+        cfg.flags = 0 if graphs else SERVER_EAGER
         h = ctypes.c_void_p(0)
         rc = lib.keccak_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != KB_OK:
@@ -522,10 +584,18 @@ def timing_enable(on: bool = True):
     _check(load_library().keccak_timing_enable(1 if on else 0))
 
 
-def timing_read() -> tuple[float, int]:
-    """(total kernel milliseconds, launches) since timing_enable()."""
+KERNELS = {"first_pass": 0, "second_pass": 1, "plain": 2, "split": 3, "tree": 4}
+
+
+def timing_read(kernel: str | None = None) -> tuple[float, int]:
+    """(total kernel milliseconds, launches) since timing_enable(), over every
+    bracketed kernel or over one kind (a key of KERNELS)."""
     ms, cnt = ctypes.c_double(0.0), ctypes.c_uint64(0)
-    _check(load_library().keccak_timing_read(ctypes.byref(ms), ctypes.byref(cnt)))
+    lib = load_library()
+    if kernel is None:
+        _check(lib.keccak_timing_read(ctypes.byref(ms), ctypes.byref(cnt)))
+    else:
+        _check(lib.keccak_timing_read_kernel(KERNELS[kernel], ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
 
 

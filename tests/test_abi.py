@@ -50,6 +50,10 @@ def test_argument_errors_need_no_device(lib):
     # unknown variant
     assert lib.keccak_batch(7, p, p, p, 4, p, None) == kb.KB_EINVAL
     assert b"variant" in lib.keccak_last_error()
+    assert lib.keccak_batch_noalloc(4, p, p, p, 4, p, None) == kb.KB_EINVAL
+    assert lib.keccak_batch_noalloc(1, p, p, p, kb.NOALLOC_MAX_MSGS + 1, p, None) == kb.KB_EINVAL
+    assert b"static workspace" in lib.keccak_last_error()
+    assert lib.keccak_batch_noalloc(1, None, None, None, 0, None, None) == kb.KB_OK
     # n == 0 is a no-op, NULLs allowed
     assert lib.keccak_batch(1, None, None, None, 0, None, None) == kb.KB_OK
     assert lib.keccak_last_error() == b""

@@ -25,12 +25,13 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def test_server_results_equal_alone_and_oracle(kb, o2):
+@pytest.mark.parametrize("graphs", [True, False])
+def test_server_results_equal_alone_and_oracle(kb, o2, graphs):
     import torch
     pool_np = wl.random_bytes(wl.rng_for(50), 1 << 24)
     pool = torch.from_numpy(pool_np).cuda()
-    _say("server: 400 requests, steps of 4096 messages, 2 in flight")
-    srv = kb.Server(pool, max_step_msgs=4096, steps_in_flight=2)
+    _say("server: 400 requests, steps of 4096 messages, 2 in flight, graphs", graphs)
+    srv = kb.Server(pool, max_step_msgs=4096, steps_in_flight=2, graphs=graphs)
     rng = np.random.Generator(np.random.PCG64(51))
     reqs = {}
     for _ in range(400):
@@ -134,6 +135,35 @@ def test_graph_replays_equal_eager(kb, mode):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, eager), rep
+        del other
+    g.close()
+
+
+def test_counted_graph_replays_each_count(kb):
+    # one capture over a fixed capacity; each replay reads the message count
+    # from device memory; every replay's digests (up to that count) equal the
+    # eager ones, and the slots past the count are left alone
+    import torch
+    b = wl.uneven(30000, 6000, seed=57)
+    data = torch.from_numpy(b.data).cuda()
+    offs = torch.from_numpy(b.offsets).cuda()
+    lens = torch.from_numpy(b.lengths).cuda()
+    var = torch.from_numpy(b.variants).cuda()
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = torch.zeros((b.n, 64), dtype=torch.uint8, device="cuda")
+    eager = kb.keccak_batch_mixed(var, data, offs, lens)
+    _say("counted graph")
+    g = kb.graph_counted(-1, data, offs, lens, count, out, variants=var)
+    for n in (b.n, 1, 0, 12345, 64, b.n + 100, 29999):
+        out.fill_(0xA5)
+        count.fill_(n)
+        other = kb.keccak_batch(1, data, offs[:500].contiguous(), lens[:500].contiguous())
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        k = min(n, b.n)
+        assert torch.equal(out[:k], eager[:k]), n
+        assert bool((out[k:] == 0xA5).all()), n
         del other
     g.close()
 

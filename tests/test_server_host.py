@@ -117,3 +117,37 @@ def test_failed_step_is_reported(kb):
             if rid in srv.poll(wait_ms=100):
                 srv.result(rid, 1)
     srv.close()
+
+
+def test_server_admits_by_byte_budget(kb, o2):
+    # a step takes requests while both its message slots and its byte budget
+    # last; a request with more bytes than a step holds is rejected at submit
+    pool = wl.random_bytes(wl.rng_for(46), 1 << 16)
+    calls = []
+
+    def run(var, offs, lens):
+        calls.append(int(lens.sum()))
+        return o2.sha3_batch_mixed(var, pool, offs, lens, threads=2)
+
+    srv = kb.Server(None, max_step_msgs=1000, steps_in_flight=1, executor=run,
+                    pool_bytes=pool.size, max_step_bytes=5000)
+    rng = np.random.Generator(np.random.PCG64(47))
+    reqs = {}
+    for _ in range(60):
+        k = int(rng.integers(1, 20))
+        lens = rng.integers(0, 250, k)
+        offs = rng.integers(0, pool.size - 250, k)
+        reqs[srv.submit(1, offs, lens)] = (offs, lens)
+    with pytest.raises(kb.KbError) as ei:
+        srv.submit(1, np.zeros(30, np.uint64), np.full(30, 200, np.uint64))
+    assert ei.value.code == kb.KB_ENOMEM
+    got = {}
+    while len(got) < len(reqs):
+        for rid in srv.poll(wait_ms=100):
+            got[rid] = srv.result(rid, reqs[rid][0].size)[0]
+    st = srv.stats()
+    srv.close()
+    assert st["rejected"] == 1 and max(calls) <= 5000 and st["steps"] > 1
+    assert sum(calls) == sum(int(l.sum()) for _, l in reqs.values())
+    for rid, (offs, lens) in reqs.items():
+        assert np.array_equal(got[rid], o2.sha3_batch_mixed(np.ones(offs.size, np.uint8), pool, offs, lens))
