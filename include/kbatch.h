@@ -67,12 +67,33 @@ enum kb_mode {
                              per message, at a fraction of the batch throughput) */
 };
 
-/* Tuning knobs of the persistent form; a zero field means "library default". */
+/*
+ * Tuning knobs of the persistent form; a zero field means "library default".
+ * Messages are grouped by block count nb = floor(L / R) + 1 into
+ * KB_NB_CLASSES classes, class c = floor(log2(nb)) capped at
+ * KB_NB_CLASSES - 1 (1, 2-3, 4-7, ..., 128 or more blocks); the class
+ * arrays give a choice per class, applied on the device to each bucket of
+ * equal block counts.
+ */
+#define KB_NB_CLASSES 8
+enum kb_staging {
+  KB_STAGING_DEFAULT = 0,
+  KB_STAGING_DIRECT = 1,   /* each block loaded when it is absorbed (fewer registers) */
+  KB_STAGING_PREFETCH = 2  /* the next block's 16-byte chunks loaded into registers while
+                              the current block is permuted (the default) */
+};
 typedef struct kb_tile {
   int32_t block_threads;    /* 0 or 256: the hashing kernels use 256-thread workgroups */
   int32_t waves_per_simd;   /* persistent grid: resident waves per SIMD (1..8) */
   int32_t steps_per_item;   /* wave-blocks of work per queue item (>= 1) */
-  int32_t reserved;
+  int32_t staging;          /* kb_staging: how a message's next block reaches the sponge */
+  int32_t class_steps[KB_NB_CLASSES];    /* per class: steps per queue item (0 = steps_per_item) */
+  int32_t class_threads[KB_NB_CLASSES];  /* per class: threads per state, 1 (one lane hashes a
+                                            message) or 5 (a five-lane group of the split form,
+                                            Section 3.2's absorb chain about twice as fast);
+                                            0 = the library's rule.  SHA-3 variants only; the
+                                            five-lane classes must be the longest ones (a class
+                                            takes 5 only if every longer class present does) */
 } kb_tile;
 
 /*
@@ -167,18 +188,57 @@ int merkle_root(int variant, const uint8_t* d_data, uint64_t total_len, uint64_t
 
 /*
  * keccak_autotune -- choose the tile of the persistent form for this batch.
- * Runs every candidate (steps_per_item in {1, 2, 4, 8, 16, 32} x
- * waves_per_simd in {1, 2, occupancy maximum}), checks that each candidate's
- * digests equal the plain form's bit for bit (a candidate that differs is
- * discarded and counted in *rejected), times the verified ones with HIP
- * events (median of `reps` runs) and returns the fastest in *best and its
- * time in *best_ms.  Arguments as keccak_batch_ex; variant -1 = mixed.
- * Synchronous; allocates two output buffers of the batch's digest size for
- * its duration.
+ * Searches, keeping the fastest so far at each stage: resident waves per
+ * SIMD {occupancy maximum, 1, 2, 3} x staging {prefetch, direct}; then
+ * steps_per_item {1, 2, 4, 8, 16, 32}; then threads per state by
+ * block-count class (the five-lane form from each class present upward, or
+ * one lane everywhere); then steps per queue item for each class present
+ * {1, 4, 16}.  Every candidate's digests are first compared with the plain
+ * form's bit for bit (a candidate that differs is discarded and counted in
+ * *rejected); the verified ones are timed with HIP events (median of `reps`
+ * runs).  The fastest goes to *best and its time to *best_ms.  Arguments as
+ * keccak_batch_ex; variant -1 = mixed.  Synchronous; allocates two output
+ * buffers of the batch's digest size for its duration.  Store the result
+ * with keccak_tune_store to have batch calls pick it up.
  */
 int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_data,
                     const uint64_t* d_offsets, const uint64_t* d_lengths, uint64_t n, int reps,
                     kb_tile* best, double* best_ms, int* rejected, hipStream_t stream);
+
+/*
+ * The autotuner's cache (a JSON file; tune_cache.cpp documents the format).
+ * Entries are keyed by (GPU architecture, ROCm version, variant, block-count
+ * class, batch class = floor(log2(n))): the launch-wide knobs
+ * (waves_per_simd, steps_per_item, staging) under block-count class "*", the
+ * per-class knobs (class_steps, class_threads) under their class.  `arch`
+ * and `rocm` name the key's device ("gfx950", "7.2"); pass both NULL for the
+ * current HIP device (its architecture without target features, and the HIP
+ * runtime's major.minor version).
+ *
+ * keccak_tune_store -- merge `tile`, as tuned for a batch of n messages of
+ * `variant` (-1 = mixed), into the cache file at `path` (created if
+ * missing), replacing entries with the same key; `ms` is recorded beside it
+ * (< 0: none).  Entries are written for the launch-wide knobs and for each
+ * class whose class_steps or class_threads is set.  KB_EINVAL for a NULL
+ * path or tile, an unknown variant, n == 0, only one of arch/rocm given, a
+ * malformed existing file or a write failure.
+ *
+ * keccak_tune_lookup -- the tile the cache at `path` (NULL: the file named
+ * by the environment variable KBATCH_TUNE) holds for a batch of n messages
+ * of `variant`: returns 1 and fills *out if any entry matches, 0 (and a zero
+ * tile) if none does or no file is named, KB_EINVAL for a malformed file.
+ *
+ * With KBATCH_TUNE set, keccak_batch, keccak_batch_mixed and keccak_batch_ex
+ * (persistent mode, tile NULL) look their batch up for the current device
+ * and run the cached tile.  keccak_last_tile -- the tile the calling
+ * thread's last such batch call ran (a zero tile: the library defaults);
+ * returns 1 if it came from the cache, else 0.
+ */
+int keccak_tune_store(const char* path, const char* arch, const char* rocm, int variant,
+                      uint64_t n, const kb_tile* tile, double ms);
+int keccak_tune_lookup(const char* path, const char* arch, const char* rocm, int variant, uint64_t n,
+                       kb_tile* out);
+int keccak_last_tile(kb_tile* out);
 
 /*
  * Keccak-p[b, n_r] (Section 3.1, eqs. 1-10; Table 1 gives the widths): apply

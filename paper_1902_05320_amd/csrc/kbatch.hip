@@ -1,32 +1,29 @@
 // libkbatch: batch SHA-3 on gfx950 -- kernels, scheduler and the C ABI.
 //
-// Pipeline of keccak_batch (persistent form), all enqueued on the caller's
-// stream with no host synchronisation:
-//   k_reset     clear histogram, cursors and control words
-//   k_count     block count nb = floor(L/R) + 1 per message and its histogram
-//               (bins 1..4094 exact, 4095 = "4095 or more"); per 64-message
-//               wave of arrival order, the lane-slots a wave would idle
-//   k_plan      one workgroup: keep arrival order if it idles <= 2 % of the
-//               lane slots, else bucket starts in descending nb (longest
-//               first) and queue-item counts per bucket (about
-//               `steps_per_item` permutations per lane each)
-//   k_fill      one thread per queue item: its message range and bucket;
-//               in the same launch, the counting-sort scatter of message
-//               indices into `order` (skipped when arrival order is kept)
-//   k_persistent  a grid sized to the resident capacity pops items from an
-//               atomic counter; each lane hashes one message per step.  The
-//               longest items run at raised wave priority so that the long
-//               absorb chains, which bound the makespan, are not slowed by
-//               round-robin issue with shorter work.
+// keccak_batch (persistent form) is two launches on the caller's stream,
+// with no host synchronisation:
+//   k_first   one 64-message chunk of arrival order per wave: a chunk of
+//             one-block messages is hashed on the spot; any other chunk is
+//             deferred (its block-count keys nb = floor(L/R) + 1 counted,
+//             bins 1..4094 exact and 4095 = "4095 or more", its index
+//             listed).
+//   k_second  a resident grid: one workgroup makes the plan (bucket starts
+//             in descending nb, longest first; queue items of about
+//             `steps_per_item` permutations per lane; the range of the
+//             longest messages that five-lane groups hash), the grid fills
+//             the queue and scatters the deferred messages into bucketed
+//             order, then hashes them: each SIMD's front wave takes the
+//             longest items (the split range first) at raised priority,
+//             the other waves the shortest ones.
 // The plain form is one k_plain launch in arrival order; the per-bucket form
-// runs the same scheduling kernels, reads the histogram back, and launches
-// k_plain once per non-empty bucket.
+// runs both passes without hashing, reads the bucket sizes back, and
+// launches k_plain once per non-empty bucket.
 //
-// Tree mode: k_tree hashes 256 leaves per workgroup and reduces them eight
-// levels in place (pairs of child digests, an unpaired last node carried up);
-// further k_tree launches reduce 256 nodes per workgroup until one is left.
-// Every level is written to its own region, so no workgroup reads a node
-// another one may overwrite.
+// Tree mode: k_tree hashes 256 leaves per workgroup and reduces them one
+// level; further k_tree launches reduce 256 nodes per workgroup up to eight
+// levels while more than 1024 remain; one 512-thread workgroup reduces the
+// rest to the root.  Every level is written to its own region, so no
+// workgroup reads a node another one may overwrite.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,7 +53,6 @@ constexpr int kBlock = 256;         // threads per workgroup of the hashing kern
 constexpr int kTreeTop = 1024;      // nodes the workgroup that reduces a tree's last levels takes
 constexpr int kTreeTopThreads = 512;  // its threads: two nodes (one pair) each at its first level
 constexpr uint32_t kKeyBins = 4096;  // block-count buckets (4095 = "4095 or more")
-constexpr uint32_t kLdsBins = 2048;  // the first pass counts keys below this in LDS
 constexpr uint32_t kScatterChunks = 64;  // deferred 64-message chunks per scatter tile
 constexpr uint32_t kLine = 64;       // 32-bit words per 256-byte line
 
@@ -71,15 +67,16 @@ enum : int {
   CTL_SPLIT_N = 6,      // bucketed order positions [0, CTL_SPLIT_N) are hashed in the split form
   CTL_SPIN_LIMIT = 7,   // set if a second-pass workgroup gave up waiting for the tiles
   CTL_USEFUL = 8,       // uint64 (words 8, 9): block counts of the deferred messages
+  CTL_DPREFIX = 16,     // words 16..24: exclusive prefix of the deferred sub-list lengths
   CTL_WORDS = 64
 };
 
 // Counters of the two passes, one 256-byte line each.
 enum : uint32_t {
-  SY_TICKET = 0,  // first-pass workgroups finished (the last one makes the plan)
-  SY_DEFER = 1,   // entries of the deferred-chunk list
-  SY_CLAIM = 2,   // second-pass tiles claimed
-  SY_DONE = 3,    // second-pass tiles finished
+  SY_EPOCH = 0,       // calls so far (the first pass's workgroup 0 counts this one)
+  SY_CLAIM = 1,       // second-pass tiles claimed
+  SY_DONE = 2,        // second-pass tiles finished
+  SY_PLAN_READY = 3,  // the epoch whose plan is complete
   kSyncCounters = 4
 };
 
@@ -101,7 +98,6 @@ constexpr uint32_t kQueueAreaDw = (kQueues + 1) * kLine;
 // workgroups' closing atomics spread over eight addresses; the plan folds
 // them and clears the copies it found dirty.
 constexpr uint32_t kCopies = 8;
-enum : uint32_t { P_USEFUL = 0, P_MAXKEY = 2, P_DIRTY = 3 };  // per copy, on its own line
 
 // Workspace metadata layout (uint32 words).  Every counter and partial sum
 // is zero between calls: the workspace is cleared when it is allocated, and
@@ -115,8 +111,8 @@ enum : uint32_t {
   M_CTL = M_IEND + kKeyBins,
   M_QUEUES = M_CTL + CTL_WORDS,
   M_SYNC = M_QUEUES + kQueueAreaDw,
-  M_PARTIALS = M_SYNC + kSyncCounters * kLine,
-  M_SIMD = M_PARTIALS + kCopies * kLine,
+  M_DEFCNT = M_SYNC + kSyncCounters * kLine,    // kCopies deferred sub-list lengths, a line each
+  M_SIMD = M_DEFCNT + kCopies * kLine,
   kMetaWords = M_SIMD + kSimdSlots
 };
 
@@ -136,12 +132,17 @@ struct PassArgs {
   uint8_t* out;
   uint64_t stride;      // output bytes per message
   uint32_t* meta;       // kMetaWords words, layout above
-  uint32_t* deferred;   // deferred chunk indices, ceil(n / 64) entries
+  uint32_t* deferred;   // deferred chunk indices: kCopies sub-lists of defer_seg entries
   uint32_t* order;      // bucketed order of the deferred messages, n entries
   WorkItem* items;      // queue items, max_items(n) entries
   uint32_t steps;       // permutations per lane in one queue item
-  uint32_t split_cap;   // most messages the split tail may take (mixed kernel)
+  uint32_t split_cap;   // most messages the split tail may take (SHA-3 variants)
+  // Per block-count class c, packed so that no array is indexed at run time
+  // (an indexed member would move the whole argument block to scratch):
+  uint64_t class_steps;    // byte c: steps per queue item (0 = `steps`)
+  uint32_t class_threads;  // nibble c: 0 = the rule, 1 = one lane, 5 = split
   uint64_t lanes;       // resident lanes of the second pass
+  uint32_t defer_seg;   // entries of each deferred sub-list (defer_seg_of(n))
   int hash;             // 0: count and scatter only (the per-bucket form)
   const uint32_t* n_dev;  // if set: the message count, read on the device (at most n)
 };
@@ -158,6 +159,17 @@ __device__ __forceinline__ int rate_of(int var) {
   return V == kMixed ? kb::rate_bytes_rt(var) : SpongeShape<V>::kMaxRate;
 }
 
+// Output bytes per message of a SHA-3 form: the digest, or the mixed form's
+// 64-byte slot.
+template <int V>
+__host__ __device__ constexpr uint32_t out_stride_of() {
+  static_assert(V <= kMixed, "SHA-3 variants and the mixed form");
+  if constexpr (V == kMixed)
+    return 64u;
+  else
+    return static_cast<uint32_t>(kb::digest_bytes_of(V));
+}
+
 template <int V>
 __device__ __forceinline__ uint64_t blocks_of(uint64_t len, int var) {
   if (V == kMixed && var > 3) return 1;  // no work: the slot is zeroed
@@ -171,14 +183,14 @@ __device__ __forceinline__ uint32_t key_of(uint64_t nb) {
 // Hash message i (`len` bytes at data + off, variant `var` in the mixed
 // form) into its output slot of `stride` bytes (the digest size, 64 in the
 // mixed form, the output length for the XOFs).
-template <int V>
+template <int V, bool PF = kb::kPrefetch<V>>
 __device__ __forceinline__ void hash_one(const uint8_t* __restrict__ data, uint64_t off,
                                          uint64_t len, int var, uint64_t i,
                                          uint8_t* __restrict__ out, uint64_t stride, uint32_t* row) {
   uint8_t* o = out + i * stride;
   if constexpr (V >= kShake128) {
     Lane A[25];
-    kb::sponge_hash<V>(A, data + off, len, var, row);
+    kb::sponge_hash<V, PF>(A, data + off, len, var, row);
     kb::squeeze_xof<V>(A, o, stride);
     return;
   }
@@ -189,7 +201,7 @@ __device__ __forceinline__ void hash_one(const uint8_t* __restrict__ data, uint6
     return;
   }
   Lane A[25];
-  kb::sponge_hash<V>(A, data + off, len, var, row);
+  kb::sponge_hash<V, PF>(A, data + off, len, var, row);
   kb::store_digest<V>(o, A, var);
 }
 
@@ -483,38 +495,24 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
 // Persistent form: two passes
 // ---------------------------------------------------------------------------
 //
-// k_first   a resident grid walks arrival order in 64-message chunks (wave w
-//           takes chunks w, w + W, w + 2W, ... of W waves).  A chunk whose
+// k_first   one 64-message chunk of arrival order per wave.  A chunk whose
 //           messages are all one block long is hashed at once: no lane
-//           idles and no ordering could shorten it.  Its digests are held
-//           in registers and stored after the next chunk's loads are
-//           issued, and the next chunk's metadata and block are loaded
-//           while this one is permuted, so every wait falls right after a
-//           permutation.  Any other chunk is deferred: its messages'
-//           block-count keys are counted and its index queued.  The last
-//           workgroup to finish makes the plan for the deferred messages
-//           (bucket starts longest first, queue items, the split range)
-//           and clears the counters the call used.
-// k_second  a resident grid first takes tiles (queue items, and the
-//           counting-sort scatter of the deferred messages into bucketed
-//           order), waits until every tile is done, then hashes: waves pop
-//           queue items (longest first) until the queue is drained.
+//           idles and no ordering could shorten it.  Any other chunk is
+//           deferred: its messages' block-count keys are counted and its
+//           index is appended to the deferred list.  The launch has no
+//           inter-workgroup synchronisation at all (the end of the kernel
+//           publishes the counts), so on a batch of one-block messages it
+//           costs what the one-thread-per-message launch costs.
+// k_second  a resident grid.  The first workgroup to arrive makes the plan
+//           for the deferred messages (bucket starts longest first, queue
+//           items, the split range) while the others wait for it; then the
+//           workgroups take tiles (queue items, and the counting-sort scatter
+//           of the deferred messages into bucketed order), wait until every
+//           tile is done, and hash: waves pop queue items (longest first)
+//           until the queue is drained.
 //
-// A batch of equal one-block messages is thus hashed in one pass with no
-// sort; the second launch finds nothing to do.
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint32_t o = __shfl_xor(v, d);
-    v = o > v ? o : v;
-  }
-  return v;
-}
+// A batch of equal one-block messages is thus hashed in the first launch
+// with no sort; the second finds an empty plan and exits.
 
 __device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -603,6 +601,18 @@ __device__ __forceinline__ uint32_t item_msgs(uint32_t key, uint32_t steps) {
   return 64u * g;
 }
 
+// Block-count class of a bucket: floor(log2(key)), capped at the last class.
+__device__ __forceinline__ uint32_t class_of_key(uint32_t key) {
+  const uint32_t c = 31u - __builtin_clz(key ? key : 1u);
+  return c < KB_NB_CLASSES - 1u ? c : KB_NB_CLASSES - 1u;
+}
+
+// Steps per queue item for a bucket: its class's tuned value, else the default.
+__device__ __forceinline__ uint32_t steps_of(const PassArgs& a, uint32_t key) {
+  const uint32_t s = static_cast<uint32_t>(a.class_steps >> (8u * class_of_key(key))) & 0xFFu;
+  return s ? s : a.steps;
+}
+
 // Bucket rank r = kKeyBins - 1 - key orders buckets longest first; in the
 // plan, thread t owns ranks 16t .. 16t + 15.
 constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
@@ -615,8 +625,8 @@ constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
 // wave) costs throughput.
 constexpr uint32_t kSplitMinKey = 32;
 
-// The plan, made by the first pass's last workgroup once every other one
-// has finished.  Folds the partial histograms and sums, writes the bucket
+// The plan, made by one workgroup of the second pass once the first pass
+// has finished.  Folds the partial histograms, writes the bucket
 // starts (longest first), the split range, the inclusive prefix of queue
 // items per rank and the tile counts, and clears every counter and partial
 // this call used, so the next call starts from zero.
@@ -624,43 +634,39 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
   uint32_t* const meta = a.meta;
   uint32_t* const ctl = meta + M_CTL;
   uint32_t* const sync = meta + M_SYNC;
-  __shared__ uint32_t s_split, s_ndef;
+  __shared__ uint32_t s_split, s_ndef, s_maxkey;
+  __shared__ unsigned long long s_useful;
   const uint32_t t = threadIdx.x;
-  uint64_t useful = 0;
-  uint32_t maxkey = 0, dirty = 0;
-#pragma unroll
-  for (uint32_t c = 0; c < kCopies; ++c) {
-    const uint32_t* pc = meta + M_PARTIALS + c * kLine;
-    const uint64_t u = (static_cast<uint64_t>(load_relaxed(pc + P_USEFUL + 1)) << 32) |
-                       load_relaxed(pc + P_USEFUL);
-    useful += u;
-    const uint32_t mk = load_relaxed(pc + P_MAXKEY);
-    maxkey = mk > maxkey ? mk : maxkey;
-    dirty |= load_relaxed(pc + P_DIRTY) ? 1u << c : 0u;
+  // The deferred sub-lists' lengths (read into a scalar register: the branch
+  // on their sum below must be uniform in the compiler's view, since
+  // barriers follow it); a copy is dirty if its sub-list is not empty.
+  uint32_t ndef_chunks = 0, dirty = 0;
+  for (uint32_t x = 0; x < kCopies; ++x) {
+    if (t == 0) ctl[CTL_DPREFIX + x] = ndef_chunks;
+    const uint32_t nx = load_relaxed(meta + M_DEFCNT + x * kLine);
+    dirty |= nx ? 1u << x : 0u;
+    ndef_chunks += nx;
   }
-  // (read into a scalar register: the branch on it below must be uniform in
-  // the compiler's view, since barriers follow it)
-  const uint32_t ndef_chunks = __builtin_amdgcn_readfirstlane(load_relaxed(&sync[SY_DEFER * kLine]));
-  __syncthreads();  // every thread has read the partials and counters
-  if (t < kCopies) {
-    uint32_t* pc = meta + M_PARTIALS + t * kLine;
-    pc[P_USEFUL] = pc[P_USEFUL + 1] = pc[P_MAXKEY] = pc[P_DIRTY] = 0u;
-  }
+  ndef_chunks = __builtin_amdgcn_readfirstlane(ndef_chunks);
+  dirty = __builtin_amdgcn_readfirstlane(dirty);
   if (t == 0) {
-    sync[SY_TICKET * kLine] = 0u;
-    sync[SY_DEFER * kLine] = 0u;
+    s_useful = 0ull;
+    s_maxkey = 0u;
+  }
+  __syncthreads();  // every thread has read the counters
+  if (t < kCopies) meta[M_DEFCNT + t * kLine] = 0u;
+  if (t == 0) {
+    ctl[CTL_DPREFIX + kCopies] = ndef_chunks;
     sync[SY_CLAIM * kLine] = 0u;
     sync[SY_DONE * kLine] = 0u;
     ctl[CTL_SPIN_LIMIT] = 0u;
-    ctl[CTL_MAXKEY] = maxkey;
-    ctl[CTL_USEFUL] = static_cast<uint32_t>(useful);
-    ctl[CTL_USEFUL + 1] = static_cast<uint32_t>(useful >> 32);
     ctl[CTL_NDEF_CHUNKS] = ndef_chunks;
   }
   if (ndef_chunks == 0) {  // every chunk was hashed by the first pass
     if (t == 0) {
       ctl[CTL_NITEMS] = ctl[CTL_TILES] = ctl[CTL_ITEM_TILES] = ctl[CTL_SPLIT_N] = 0u;
       ctl[CTL_PRIO_KEY] = 0xFFFFFFFFu;
+      ctl[CTL_MAXKEY] = ctl[CTL_USEFUL] = ctl[CTL_USEFUL + 1] = 0u;
     }
     return;
   }
@@ -699,25 +705,36 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) dst[v] = make_uint4(0u, 0u, 0u, 0u);
     }
-  uint32_t cnt[kRanksPerThread], st[kRanksPerThread], c_sum = 0;
+  uint32_t cnt[kRanksPerThread], st[kRanksPerThread], c_sum = 0, kmax = 0;
+  uint64_t ublocks = 0;  // blocks of this thread's buckets (a key of 4095 counts 4095)
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);  // = lo + 15 - q
     cnt[q] = key ? byk[kRanksPerThread - 1u - q] : 0u;
     c_sum += cnt[q];
+    ublocks += static_cast<uint64_t>(key) * cnt[q];
+    if (cnt[q] && key > kmax) kmax = key;
   }
-  const uint32_t c_incl = block_inclusive_scan(c_sum, scratch);
+  if (ublocks) atomicAdd(&s_useful, static_cast<unsigned long long>(ublocks));
+  if (kmax) atomicMax(&s_maxkey, kmax);
+  const uint32_t c_incl = block_inclusive_scan(c_sum, scratch);  // (its barriers order the above)
   uint32_t c_base = c_incl - c_sum;
   if (t == kBlock - 1) s_ndef = c_incl;
   __syncthreads();
   const uint32_t ndef = __builtin_amdgcn_readfirstlane(s_ndef);  // deferred messages
+  const uint64_t useful = s_useful;                              // their blocks
+  if (t == 0) {
+    ctl[CTL_MAXKEY] = s_maxkey;
+    ctl[CTL_USEFUL] = static_cast<uint32_t>(useful);
+    ctl[CTL_USEFUL + 1] = static_cast<uint32_t>(useful >> 32);
+  }
   const uint64_t avg = useful / (ndef ? ndef : 1u);
   // bucket starts; the split range ends where the keys drop below kmin
   const uint64_t per_lane = 2u * useful / (a.lanes ? a.lanes : 1u);
   uint64_t kmin64 = 4u * avg > kSplitMinKey ? 4u * avg : kSplitMinKey;
   if (per_lane > kmin64) kmin64 = per_lane;
   const uint32_t kmin = kmin64 < kKeyBins - 1u ? static_cast<uint32_t>(kmin64) : kKeyBins - 1u;
-  if (t == 0) s_split = ndef;  // every key at least kmin
+  if (t == 0) s_split = ndef;  // until a bucket that stays one lane per message
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
@@ -726,10 +743,16 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
     c_base += cnt[q];
   }
   __syncthreads();
+  // A bucket goes to the split form if its class's tile says five threads
+  // per state, or (no choice given) by the rule key >= kmin.  The split range
+  // is the longest-first prefix of such buckets: it ends at the start of the
+  // first non-empty bucket that stays one lane per message.
 #pragma unroll
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
-    if (key == kmin - 1u) s_split = st[q];  // messages in buckets of key >= kmin
+    const uint32_t ct = (a.class_threads >> (4u * class_of_key(key))) & 0xFu;
+    const bool split_here = ct == 5u || (ct == 0u && key >= kmin);
+    if (cnt[q] && !split_here) atomicMin(&s_split, st[q]);
   }
   __syncthreads();
   const uint32_t split_all = __builtin_amdgcn_readfirstlane(s_split);
@@ -740,7 +763,7 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
     const uint32_t b = st[q] > split ? st[q] : split, e = st[q] + cnt[q];
-    const uint32_t per = item_msgs(key, a.steps);
+    const uint32_t per = item_msgs(key, steps_of(a, key));
     items[q] = e > b ? (e - b + per - 1u) / per : 0u;
     it_sum += items[q];
   }
@@ -768,155 +791,100 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
 }
 
 // Waves per SIMD the first pass is compiled for: three for the fixed
-// variants (the register allocator then fits the permutation, the next
-// chunk's block in flight and two chunks of metadata in 168 VGPRs without
-// spilling); the mixed form needs more registers, and SHAKE128's 168-byte
-// rate more LDS, so those hold two.
+// variants and the mixed form (the permutation, the staging and a chunk's
+// metadata fit in 168 VGPRs); SHAKE128's 168-byte rate needs more LDS, so it
+// holds two.
 template <int V>
-constexpr int kFirstWaves = V == kMixed || V == kShake128 ? 2 : 3;
+constexpr int kFirstWaves = V == kShake128 ? 2 : 3;
 
-// First pass (see above).  a.hash == 0 defers every chunk (the per-bucket
-// form hashes nothing here).
+// Deferral bookkeeping, by the deferring wave alone.  With no barrier, a
+// launch whose chunks are all hashed runs like the one-thread-per-message
+// launch (the two workgroup barriers an LDS histogram needs made the
+// uniform batch 23 % slower, measured).  The wave counts its keys into
+// the partial histogram of its copy with one atomic per distinct key
+// (lanes of equal keys found by ballot) and appends its chunk to its copy's
+// deferred sub-list.  The plan derives the block sums from the histogram,
+// so no per-wave sums contend for one line.
+// Out of line, so that the hashing path stays one straight run of code
+// right after the metadata loads: with this code inlined between them the
+// uniform batch ran 20 % slower although the permutation's code was byte
+// for byte the same (measured twice, with the blocks in either order).
+// (Arguments by value: a reference to the argument block would move it to
+// scratch.)
+template <int V>
+__device__ __attribute__((noinline)) void defer_chunk(uint32_t* meta, uint32_t* deferred, uint32_t seg,
+                                                    uint32_t len, int var, uint64_t c, bool valid,
+                                                    uint32_t lane) {
+  const uint32_t x = blockIdx.x % kCopies;
+  uint32_t* const hist = meta + M_HIST + x * kKeyBins;
+  const uint32_t key = valid ? key_of(blocks_of<V>(len, var)) : 0u;
+  uint64_t todo = __builtin_amdgcn_ballot_w64(valid);
+  while (todo) {  // wave-uniform: one pass per distinct key
+    const uint32_t leader = static_cast<uint32_t>(__builtin_ctzll(todo));
+    const uint32_t k = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t same = __builtin_amdgcn_ballot_w64(valid && key == k) & todo;
+    if (lane == leader) atomicAdd(&hist[k], static_cast<uint32_t>(__builtin_popcountll(same)));
+    todo &= ~same;
+  }
+  if (lane == 0) {
+    const uint32_t slot = atomicAdd(&meta[M_DEFCNT + x * kLine], 1u);
+    deferred[static_cast<uint64_t>(x) * seg + slot] = static_cast<uint32_t>(c);
+  }
+}
+
+// First pass (see above), grid = ceil(n / 256): wave w of workgroup g takes
+// chunk 4g + w.  a.hash == 0 defers every chunk (the per-bucket form hashes
+// nothing here).
 template <int V>
 __global__ __launch_bounds__(kBlock, kFirstWaves<V>) void k_first(PassArgs a) {
   using S = SpongeShape<V>;
   a.n = pass_count(a);
+  // the staging rows only: 40 KiB for the 136- and 144-byte rates, so four
+  // workgroups fit on a CU
   __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
-  __shared__ uint32_t lhist[kLdsBins];
-  __shared__ unsigned long long luseful;
-  __shared__ uint32_t lmax, last;
-  uint32_t* const row = lds + threadIdx.x * S::kRowDw;
-  uint32_t* const hist = a.meta + M_HIST + (blockIdx.x % kCopies) * kKeyBins;
   uint32_t* const sync = a.meta + M_SYNC;
-  for (uint32_t k = threadIdx.x; k < kLdsBins; k += kBlock) lhist[k] = 0u;
-  if (threadIdx.x == 0) {
-    luseful = 0ull;
-    lmax = 0u;
-  }
-  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) sync[SY_EPOCH * kLine] += 1u;  // read by the second pass
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t nch = (a.n + 63u) / 64u;
-  const uint64_t W = static_cast<uint64_t>(gridDim.x) * (kBlock / 64);
-  const uint64_t c0 = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64u;
-  // Deferred chunks not yet in the global list: lane k holds entry k.
-  uint32_t dbuf = 0, dcnt = 0;
-  uint64_t useful = 0;  // block counts of the deferred messages (wave-uniform)
-  uint32_t kmax = 0;
-  auto flush = [&]() {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&sync[SY_DEFER * kLine], dcnt);
-    base = __builtin_amdgcn_readfirstlane(__shfl(base, 0));
-    if (lane < dcnt) a.deferred[base + lane] = dbuf;
-    dcnt = 0;
-  };
-  auto defer = [&](const ChunkMeta& m, uint64_t c) {
-    const bool valid = lane_valid(a, c, lane);
-    const uint32_t key = valid ? key_of(blocks_of<V>(m.len, m.var)) : 0u;
-    if (valid) {
-      if (key < kLdsBins)
-        atomicAdd(&lhist[key], 1u);
-      else
-        atomicAdd(&hist[key], 1u);
-    }
-    useful += __builtin_amdgcn_readfirstlane(wave_sum(key));
-    const uint32_t mx = __builtin_amdgcn_readfirstlane(wave_max(key));
-    kmax = mx > kmax ? mx : kmax;
-    if (lane == dcnt) dbuf = static_cast<uint32_t>(c);
-    if (++dcnt == 64u) flush();
-  };
-  // one-block messages only: the length is the block's message bytes
-  auto load = [&](kb::BlockChunks<V>& b, const ChunkMeta& m, uint64_t c) {
-    kb::load_block<V>(b, a.data + m.off, lane_valid(a, c, lane) ? m.len : 0u);
-  };
-  ChunkMeta m0, m1;
+  // (the wave index through readfirstlane: the compiler then sees the chunk
+  // and every decision on it as wave-uniform, and branches on scalars)
+  const uint64_t c = static_cast<uint64_t>(blockIdx.x) * (kBlock / 64) +
+                     __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
+  const bool in = c < nch;
+  ChunkMeta m;
+  load_meta<V>(m, a, in ? c : 0u, lane);
+  const bool valid = in && lane_valid(a, c, lane);
+  const bool h = in && a.hash && one_block_chunk<V>(m, valid);  // wave-uniform
+  const bool d = in && !h;
   kb::BlockChunks<V> bc;
-  load_meta<V>(m0, a, c0, lane);
-  load_meta<V>(m1, a, c0 + W, lane);
-  bool h0 = false;
-  if (c0 < nch) {
-    h0 = a.hash && one_block_chunk<V>(m0, lane_valid(a, c0, lane));
-    if (h0)
-      load(bc, m0, c0);
-    else
-      defer(m0, c0);
+  if (h) kb::load_block<V>(bc, a.data + m.off, valid ? m.len : 0u);
+  if (!h) {
+    if (d) defer_chunk<V>(a.meta, a.deferred, a.defer_seg, m.len, m.var, c, valid, lane);
+    return;
   }
-  uint32_t dig[S::kMaxDigestDw > 0 ? S::kMaxDigestDw : 1];
-  // dig holds the digests of chunk `pend` until the next chunk is staged
-  uint64_t pend = ~0ull;
-  auto put = [&]() {
-    if constexpr (V < kShake128) {
-      if (pend != ~0ull && lane_valid(a, pend, lane)) put_digest<V>(a.out + (pend * 64u + lane) * a.stride, dig);
-    }
-    pend = ~0ull;
-  };
-  for (uint64_t c = c0; c < nch; c += W) {
-    Lane A[25];
-    if (h0) {  // stage chunk c's block and absorb it into the zero state
-      uint32_t w[S::kMaxRateDw];
-      kb::stage_block<V>(row, bc, lane_valid(a, c, lane) ? m0.len : 0u, rate_of<V>(m0.var), true, w);
-      const int RW = rate_of<V>(m0.var) / 4;
+  // stage the block, absorb it into the zero state, permute, squeeze
+  uint32_t* const row = lds + threadIdx.x * S::kRowDw;
+  Lane A[25];
+  uint32_t w[S::kMaxRateDw];
+  kb::stage_block<V>(row, bc, valid ? m.len : 0u, rate_of<V>(m.var), true, w);
+  const int RW = rate_of<V>(m.var) / 4;
 #pragma unroll
-      for (int k = 0; k < 50; ++k) {
-        const uint32_t v = (k < S::kMaxRateDw && k < RW) ? w[k < S::kMaxRateDw ? k : 0] : 0u;
-        if (k & 1)
-          A[k >> 1].hi = v;
-        else
-          A[k >> 1].lo = v;
-      }
-    }
-    put();  // the previous chunk's digests: issued after the wait above, before the loads below
-    // chunk c + W: decide, and start its block's loads; metadata of c + 2W
-    const uint64_t c1 = c + W;
-    bool h1 = false;
-    if (c1 < nch) {
-      h1 = a.hash && one_block_chunk<V>(m1, lane_valid(a, c1, lane));
-      if (h1)
-        load(bc, m1, c1);
-      else
-        defer(m1, c1);
-    }
-    ChunkMeta m2;
-    load_meta<V>(m2, a, c1 + W, lane);
-    if (h0) {
-      kb::keccak_rounds_0_22(A);
-      kb::keccak_round(A, 23);
-      if constexpr (V >= kShake128) {
-        if (lane_valid(a, c, lane)) kb::squeeze_xof<V>(A, a.out + (c * 64u + lane) * a.stride, a.stride);
-      } else {
-        take_digest<V>(dig, A, m0.var);
-        pend = c;
-      }
-    }
-    m0 = m1;
-    m1 = m2;
-    h0 = h1;
+  for (int k = 0; k < 50; ++k) {
+    const uint32_t v = (k < S::kMaxRateDw && k < RW) ? w[k < S::kMaxRateDw ? k : 0] : 0u;
+    if (k & 1)
+      A[k >> 1].hi = v;
+    else
+      A[k >> 1].lo = v;
   }
-  put();
-  if (dcnt) flush();
-  if (lane == 0) {
-    if (useful) atomicAdd(&luseful, static_cast<unsigned long long>(useful));
-    atomicMax(&lmax, kmax);
+  kb::keccak_rounds_0_22(A);
+  kb::keccak_round(A, 23);
+  if constexpr (V >= kShake128) {
+    if (valid) kb::squeeze_xof<V>(A, a.out + (c * 64u + lane) * a.stride, a.stride);
+  } else {
+    uint32_t dig[S::kMaxDigestDw];
+    take_digest<V>(dig, A, m.var);
+    if (valid) put_digest<V>(a.out + (c * 64u + lane) * a.stride, dig);
   }
-  __syncthreads();
-  for (uint32_t k = threadIdx.x; k < kLdsBins; k += kBlock)
-    if (lhist[k]) atomicAdd(&hist[k], lhist[k]);
-  if (threadIdx.x == 0 && luseful) {
-    uint32_t* pc = a.meta + M_PARTIALS + (blockIdx.x % kCopies) * kLine;
-    atomicAdd(reinterpret_cast<unsigned long long*>(pc + P_USEFUL), luseful);
-    atomicMax(pc + P_MAXKEY, lmax);
-    atomicOr(pc + P_DIRTY, 1u);
-  }
-  // the last workgroup to get here makes the plan
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&sync[SY_TICKET * kLine], 1u) == gridDim.x - 1u ? 1u : 0u;
-  __syncthreads();
-  // values broadcast through LDS are read with readfirstlane wherever a
-  // branch on them precedes a barrier: the compiler must see the branch as
-  // uniform, or it may restructure the barriers into divergent code
-  if (!__builtin_amdgcn_readfirstlane(last)) return;
-  __threadfence();
-  make_plan(a, lds);
 }
 
 // Queue item q of the second pass: its bucket (the smallest rank r with
@@ -936,7 +904,7 @@ __device__ __forceinline__ void items_tile(const PassArgs& a, uint32_t tile) {
       lo = mid + 1;
   }
   const uint32_t key = kKeyBins - 1u - lo;
-  const uint32_t per = item_msgs(key, a.steps);
+  const uint32_t per = item_msgs(key, steps_of(a, key));
   const uint32_t first_item = lo ? iend[lo - 1] : 0u;
   const uint32_t split = ctl[CTL_SPLIT_N];  // positions before it are split work
   const uint32_t start = meta[M_START + key];
@@ -964,7 +932,12 @@ __device__ __forceinline__ void scatter_tile(const PassArgs& a, uint32_t tile, u
     msg[q] = ~0ull;
     keys[q] = 0u;
     if (first + slot < nchunks) {
-      const uint64_t i = static_cast<uint64_t>(a.deferred[first + slot]) * 64u + lane;
+      const uint32_t j = first + slot;  // in the sub-lists end to end
+      uint32_t x = 0;
+#pragma unroll
+      for (uint32_t y = 1; y < kCopies; ++y) x = j >= a.meta[M_CTL + CTL_DPREFIX + y] ? y : x;
+      const uint32_t e = j - a.meta[M_CTL + CTL_DPREFIX + x];
+      const uint64_t i = static_cast<uint64_t>(a.deferred[static_cast<uint64_t>(x) * a.defer_seg + e]) * 64u + lane;
       if (i < a.n) {
         msg[q] = i;
         keys[q] = key_at<V>(a.lens, a.vars, i);
@@ -1002,7 +975,7 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 // twice.  A wave drains the sub-queue of its own XCD first and then the
 // others in turn, so every item is taken whatever the mapping of waves to
 // XCDs, and every wave leaves once all sub-queues are empty.
-template <int V>
+template <int V, bool PF = kb::kPrefetch<V>>
 __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
   using S = SpongeShape<V>;
   a.n = pass_count(a);
@@ -1014,9 +987,42 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
                 "a wave's staging rows hold its split exchange area");
   const uint32_t* ctl = a.meta + M_CTL;
   uint32_t* const sync = a.meta + M_SYNC;
-  const uint32_t tiles = ctl[CTL_TILES];
-  if (tiles == 0) return;  // the first pass hashed everything
-  const uint32_t item_tiles = ctl[CTL_ITEM_TILES];
+  // The plan for this call (epoch E, counted by the first pass) is made by
+  // workgroup 0, which the dispatcher starts first, so it is always running;
+  // the others wait until it publishes E (electing the planner with an
+  // atomic on one word cost tens of microseconds: hundreds of workgroups
+  // contending for it).  The published word also says whether there is any
+  // work: when there is none (the first pass hashed every chunk), the waiting
+  // workgroups leave without an acquire fence, which on this chip
+  // invalidates the L2 and, in hundreds of workgroups at once, took about
+  // 0.1 ms.  The wait is bounded (kSpinLimit sleeps, with relaxed loads); a
+  // workgroup that gives up flags it and leaves.
+  const uint32_t epoch = __builtin_amdgcn_readfirstlane(load_relaxed(&sync[SY_EPOCH * kLine])) & 0x7FFFFFFFu;
+  uint32_t* const ready = &sync[SY_PLAN_READY * kLine];  // (epoch << 1) | any work
+  if (blockIdx.x == 0) {
+    make_plan(a, lds);
+    __syncthreads();  // every thread's plan writes are done
+    if (threadIdx.x == 0)
+      __hip_atomic_store(ready, (epoch << 1) | (ctl[CTL_TILES] ? 1u : 0u), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    if (!__builtin_amdgcn_readfirstlane(ctl[CTL_TILES])) return;  // the first pass hashed everything
+  } else {
+    if (threadIdx.x == 0) {
+      uint32_t spins = 0, r = load_relaxed(ready);
+      while ((r >> 1) != epoch && spins < kSpinLimit) {
+        __builtin_amdgcn_s_sleep(8);
+        ++spins;
+        r = load_relaxed(ready);
+      }
+      s_gave_up = (r >> 1) != epoch ? 2u : (r & 1u);  // 2: gave up, 0: nothing to do, 1: work
+      if (s_gave_up == 2u) a.meta[M_CTL + CTL_SPIN_LIMIT] = 1u;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_gave_up) != 1u) return;
+    __threadfence();  // acquire: the plan is visible from here on
+  }
+  const uint32_t tiles = __builtin_amdgcn_readfirstlane(load_relaxed(&ctl[CTL_TILES]));
+  const uint32_t item_tiles = load_relaxed(&ctl[CTL_ITEM_TILES]);
   // Tiles are claimed one at a time from a counter.  One thread claims and
   // reports; the loop condition is a scalar read after a barrier, so the
   // loop (with the barriers in it) is uniform as the compiler sees it.
@@ -1069,10 +1075,9 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
   // positions [0, split_n)) eight at a time, one per 8-lane group, in the
   // lane-split form, whose chain of permutations runs about twice as fast.
   // The exchange area is this wave's own staging rows.
-  // (compiled into the mixed-variant kernel only: in the fixed-variant ones
-  // the extra code alone slowed the one-block uniform batch by 8 %)
-  const uint32_t split_n = V == kMixed ? ctl[CTL_SPLIT_N] : 0u;
-  if constexpr (V == kMixed) {
+  // (SHA-3 variants; the XOFs keep one lane per message)
+  const uint32_t split_n = V <= kMixed ? ctl[CTL_SPLIT_N] : 0u;
+  if constexpr (V <= kMixed) {
     if (front && split_n) {
       namespace sp = kb::split;
       uint64_t* area = reinterpret_cast<uint64_t*>(lds + (threadIdx.x & ~63u) * S::kRowDw);
@@ -1081,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
       __asm__ volatile("" ::: "memory");
       sp::SplitLane L;
       sp::setup(L, lane % sp::kGroupLanes, area + (lane / sp::kGroupLanes) * sp::kGroupSlots, zero);
-      const int slot_dw = 16;
+      const int slot_dw = static_cast<int>(out_stride_of<V>() / 4u);
       uint32_t* split_ctr = reinterpret_cast<uint32_t*>(queues + kQueues * (kLine / 2));
       __builtin_amdgcn_s_setprio(3);
       for (;;) {
@@ -1093,9 +1098,9 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
         const uint32_t pos = d * kSplitGroups + lane / sp::kGroupLanes;
         if (pos < split_n) {
           const uint32_t i = a.order[pos];
-          const int var = a.vars[i];
+          const int var = V == kMixed ? a.vars[i] : V;
           uint32_t* o = reinterpret_cast<uint32_t*>(a.out + static_cast<uint64_t>(i) * a.stride);
-          if (var > 3) {
+          if (V == kMixed && var > 3) {
             Lane z[5];
 #pragma unroll
             for (int j = 0; j < 5; ++j) z[j] = Lane{0u, 0u};
@@ -1154,7 +1159,7 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
         lenn = a.lens[in];
         if constexpr (V == kMixed) varn = a.vars[in];
       }
-      hash_one<V>(a.data, off, len, var, i, a.out, a.stride, row);
+      hash_one<V, PF>(a.data, off, len, var, i, a.out, a.stride, row);
       pos = pn;
       i = in;
       off = offn;
@@ -1292,6 +1297,14 @@ int grow(void** ptr, uint64_t* cap, uint64_t need, hipStream_t stream) {
   return KB_OK;
 }
 
+// Deferred chunks are listed per partial copy (copy = first-pass workgroup
+// index mod kCopies, so that the appends of different copies go to different
+// counters): copy x's workgroups hold at most 4 * ceil(ceil(n / 256) / 8)
+// chunks, the length of each sub-list.
+constexpr uint64_t defer_seg_of(uint64_t n) {
+  return 4u * (((n + kBlock - 1) / kBlock + kCopies - 1) / kCopies);
+}
+
 // Queue items of a batch of n messages: at most ceil(n / 64) whole ones and
 // one partial item per bucket.
 uint64_t max_items(uint64_t n) { return n / 64 + kKeyBins + 1; }
@@ -1310,7 +1323,7 @@ int grow_batch(Workspace& w, uint64_t msgs, hipStream_t stream) {
   if (!rc)
     rc = grow(reinterpret_cast<void**>(&w.items), &w.items_cap, max_items(msgs) * sizeof(WorkItem),
               stream);
-  if (!rc) rc = grow(reinterpret_cast<void**>(&w.deferred), &w.deferred_cap, (msgs + 63) / 64 * 4ull, stream);
+  if (!rc) rc = grow(reinterpret_cast<void**>(&w.deferred), &w.deferred_cap, kCopies * defer_seg_of(msgs) * 4ull, stream);
   return rc;
 }
 
@@ -1399,6 +1412,17 @@ int resident_grid(const void* kernel, const kb_tile* tile, int cus, uint32_t* gr
   return KB_OK;
 }
 
+// The second pass for a tile's staging form: blocks loaded when absorbed
+// (KB_STAGING_DIRECT, SHA-3 variants) or the next block prefetched into
+// registers while the current one is permuted.
+template <int V>
+const void* second_pass_kernel(const kb_tile* tile) {
+  if constexpr (V <= kMixed) {
+    if (tile && tile->staging == KB_STAGING_DIRECT) return reinterpret_cast<const void*>(&k_second<V, false>);
+  }
+  return reinterpret_cast<const void*>(&k_second<V, true>);
+}
+
 // The persistent form (two passes) or, with mode KB_MODE_PER_BUCKET, the
 // same passes without hashing followed by one plain launch per bucket, the
 // bucket sizes read back on the host.
@@ -1411,8 +1435,12 @@ int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hi
   int rc = cu_count(dev, &cus);
   if (rc) return rc;
   uint32_t grid1 = 0, grid2 = 0;
-  rc = resident_grid(reinterpret_cast<const void*>(&k_first<V>), tile, cus, &grid1);
-  if (!rc) rc = resident_grid(reinterpret_cast<const void*>(&k_second<V>), tile, cus, &grid2);
+  // first pass: one 64-message chunk per wave
+  const uint64_t g1 = (b.n + kBlock - 1) / kBlock;
+  if (g1 > 0x7FFFFFFFull) return fail(KB_EINVAL, "batch too large for one launch");
+  grid1 = static_cast<uint32_t>(g1 ? g1 : 1);
+  const void* second = second_pass_kernel<V>(tile);
+  if (!rc) rc = resident_grid(second, tile, cus, &grid2);
   if (rc) return rc;
   PassArgs a{};
   a.data = b.data;
@@ -1424,13 +1452,19 @@ int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hi
   a.stride = b.stride;
   a.meta = w.meta;
   a.deferred = w.deferred;
+  a.defer_seg = static_cast<uint32_t>(defer_seg_of(b.n));
   a.order = w.order;
   a.items = w.items;
   a.steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 4u;
   // at most eight split messages per SIMD: one 8-group split item for each
-  // SIMD's front wave (mixed-variant kernel only; the per-bucket form takes
-  // none)
-  a.split_cap = V == kMixed && !per_bucket ? 8u * 4u * static_cast<uint32_t>(cus) : 0u;
+  // SIMD's front wave (SHA-3 variants; the per-bucket form takes none)
+  a.split_cap = V <= kMixed && !per_bucket ? 8u * 4u * static_cast<uint32_t>(cus) : 0u;
+  a.class_steps = 0;
+  a.class_threads = 0;
+  for (int c = 0; tile && c < KB_NB_CLASSES; ++c) {  // ranges checked by check_tile
+    a.class_steps |= static_cast<uint64_t>(tile->class_steps[c] & 0xFF) << (8 * c);
+    a.class_threads |= static_cast<uint32_t>(tile->class_threads[c] & 0xF) << (4 * c);
+  }
   a.lanes = static_cast<uint64_t>(grid2) * kBlock;
   a.hash = per_bucket ? 0 : 1;
   a.n_dev = n_dev;
@@ -1441,7 +1475,8 @@ int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hi
   KB_HIP(hipGetLastError());
   {
     TimedLaunch tl(s, KB_KERNEL_SECOND_PASS);
-    hipLaunchKernelGGL(k_second<V>, dim3(grid2), dim3(kBlock), 0, s, a);
+    void* args[] = {&a};
+    KB_HIP(hipLaunchKernel(second, dim3(grid2), dim3(kBlock), args, 0, s));
   }
   KB_HIP(hipGetLastError());
   if (!per_bucket) return KB_OK;
@@ -1503,15 +1538,47 @@ int check_batch(const Batch& b, int mode) {
   return KB_OK;
 }
 
+// A tile's fields must lie in their documented ranges.
+int check_tile(const kb_tile* t) {
+  if (!t) return KB_OK;
+  if (t->block_threads != 0 && t->block_threads != kBlock)
+    return fail(KB_EINVAL, "tile.block_threads must be 0 or %d", kBlock);
+  if (t->waves_per_simd < 0 || t->waves_per_simd > 8)
+    return fail(KB_EINVAL, "tile.waves_per_simd must be in 0..8");
+  if (t->steps_per_item < 0 || t->steps_per_item > 255)
+    return fail(KB_EINVAL, "tile.steps_per_item must be in 0..255");
+  if (t->staging < KB_STAGING_DEFAULT || t->staging > KB_STAGING_PREFETCH)
+    return fail(KB_EINVAL, "tile.staging must be a kb_staging value");
+  for (int c = 0; c < KB_NB_CLASSES; ++c) {
+    if (t->class_steps[c] < 0 || t->class_steps[c] > 255)
+      return fail(KB_EINVAL, "tile.class_steps[%d] must be in 0..255", c);
+    if (t->class_threads[c] != 0 && t->class_threads[c] != 1 && t->class_threads[c] != 5)
+      return fail(KB_EINVAL, "tile.class_threads[%d] must be 0, 1 or 5", c);
+  }
+  return KB_OK;
+}
+
 int batch_entry(int variant, const uint8_t* vars, const uint8_t* data, const uint64_t* offs,
                 const uint64_t* lens, uint64_t n, uint8_t* out, int mode, const kb_tile* tile,
                 hipStream_t s) {
   g_err.clear();
-  if (tile && tile->block_threads != 0 && tile->block_threads != kBlock)
-    return fail(KB_EINVAL, "tile.block_threads must be 0 or %d", kBlock);
+  if (int rc = check_tile(tile)) return rc;
   Batch b{variant, vars, data, offs, lens, n, out, out_stride(variant)};
   int rc = check_batch(b, mode);
   if (rc || n == 0) return rc;
+  // With no tile given, the autotuner's cache (KBATCH_TUNE) may hold one for
+  // this batch; a malformed cache file is an error, not a silent default.
+  kb_tile cached;
+  int from_cache = 0;
+  if (!tile && mode == KB_MODE_PERSISTENT && variant <= kMixed) {
+    from_cache = kb::tune_lookup(nullptr, variant == kMixed ? -1 : variant, n, &cached);
+    if (from_cache < 0) return from_cache;
+    if (from_cache) {
+      if ((rc = check_tile(&cached))) return rc;
+      tile = &cached;
+    }
+  }
+  kb::note_tile(tile, from_cache);
   return dispatch(b, mode, tile, s);
 }
 
@@ -1689,7 +1756,7 @@ constexpr uint64_t kScratchOrderOff = align256(uint64_t{kMetaWords} * 4u);
 constexpr uint64_t kScratchItemsOff = kScratchOrderOff + align256(kNoAllocMax * 4u);
 constexpr uint64_t kScratchDeferredOff =
     kScratchItemsOff + align256((kNoAllocMax / 64 + kKeyBins + 1) * sizeof(WorkItem));
-constexpr uint64_t kScratchBytes = kScratchDeferredOff + align256((kNoAllocMax + 63) / 64 * 4u);
+constexpr uint64_t kScratchBytes = kScratchDeferredOff + align256(kCopies * defer_seg_of(kNoAllocMax) * 4u);
 }  // namespace
 
 static __device__ __align__(256) uint8_t scratch[kScratchBytes];
@@ -1723,7 +1790,7 @@ int scratch_ws(hipStream_t stream, Workspace* w) {
   w->items = reinterpret_cast<WorkItem*>(base + kScratchItemsOff);
   w->items_cap = (kNoAllocMax / 64 + kKeyBins + 1) * sizeof(WorkItem);
   w->deferred = reinterpret_cast<uint32_t*>(base + kScratchDeferredOff);
-  w->deferred_cap = (kNoAllocMax + 63) / 64 * 4u;
+  w->deferred_cap = kCopies * defer_seg_of(kNoAllocMax) * 4u;
   return KB_OK;
 }
 }  // namespace
@@ -1840,6 +1907,7 @@ int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_dat
                        KB_MODE_PERSISTENT);
   if (rc) return rc;
   if (n == 0) return fail(KB_EINVAL, "nothing to tune on an empty batch");
+  if (n >= 0xFFFFFFFFull) return fail(KB_EINVAL, "the persistent form takes fewer than 2^32 messages");
   if (reps < 1) reps = 1;
   const uint64_t bytes = n * out_stride(v);
   uint8_t *ref = nullptr, *cand = nullptr;
@@ -1868,63 +1936,115 @@ int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_dat
     cleanup();
     return rc;
   }
-  const int steps_c[] = {1, 2, 4, 8, 16, 32};
-  const int waves_c[] = {1, 2, 0};  // 0 = occupancy maximum
-  double best_t = -1.0;
   int nrej = 0;
-  for (int sp : steps_c)
-    for (int wv : waves_c) {
-      kb_tile t{};
-      t.steps_per_item = sp;
-      t.waves_per_simd = wv;
-      b.out = cand;
-      // parity gate: the candidate's digests must equal the plain form's
-      if (hipMemsetAsync(cand, 0xA5, bytes, stream) != hipSuccess ||
-          hipMemsetAsync(mism, 0, sizeof(unsigned long long), stream) != hipSuccess) {
-        cleanup();
-        return fail(KB_EHIP, "hipMemsetAsync failed");
-      }
-      rc = dispatch(b, KB_MODE_PERSISTENT, &t, stream);
-      if (rc) {
-        cleanup();
-        return rc;
-      }
-      hipLaunchKernelGGL(k_compare, dim3(1024), dim3(kBlock), 0, stream,
-                         reinterpret_cast<const uint32_t*>(ref), reinterpret_cast<const uint32_t*>(cand),
-                         bytes / 4, mism);
-      unsigned long long bad = 0;
-      if (hipMemcpyAsync(&bad, mism, sizeof bad, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-          hipStreamSynchronize(stream) != hipSuccess) {
-        cleanup();
-        return fail(KB_EHIP, "autotune parity check failed to run");
-      }
-      if (bad) {
-        ++nrej;
-        continue;
-      }
-      std::vector<double> ts;
-      for (int r = 0; r < reps; ++r) {
-        (void)hipEventRecord(e0, stream);
-        rc = dispatch(b, KB_MODE_PERSISTENT, &t, stream);
-        (void)hipEventRecord(e1, stream);
-        if (rc || hipEventSynchronize(e1) != hipSuccess) {
-          cleanup();
-          return rc ? rc : fail(KB_EHIP, "autotune timing failed");
-        }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ts.push_back(ms);
-      }
-      const double tm = median(ts);
-      if (best_t < 0.0 || tm < best_t) {
-        best_t = tm;
-        *best = t;
-      }
+  // Run one candidate: its digests must equal the plain form's bit for bit
+  // (else it is rejected, < 0), then the median of `reps` timed runs.
+  auto trial = [&](const kb_tile& t, double* ms) -> int {
+    *ms = -1.0;
+    b.out = cand;
+    if (hipMemsetAsync(cand, 0xA5, bytes, stream) != hipSuccess ||
+        hipMemsetAsync(mism, 0, sizeof(unsigned long long), stream) != hipSuccess)
+      return fail(KB_EHIP, "hipMemsetAsync failed");
+    int r = dispatch(b, KB_MODE_PERSISTENT, &t, stream);
+    if (r) return r;
+    hipLaunchKernelGGL(k_compare, dim3(1024), dim3(kBlock), 0, stream,
+                       reinterpret_cast<const uint32_t*>(ref), reinterpret_cast<const uint32_t*>(cand),
+                       bytes / 4, mism);
+    unsigned long long bad = 0;
+    if (hipMemcpyAsync(&bad, mism, sizeof bad, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return fail(KB_EHIP, "autotune parity check failed to run");
+    if (bad) {
+      ++nrej;
+      return KB_OK;
     }
+    std::vector<double> ts;
+    for (int k = 0; k < reps; ++k) {
+      (void)hipEventRecord(e0, stream);
+      r = dispatch(b, KB_MODE_PERSISTENT, &t, stream);
+      (void)hipEventRecord(e1, stream);
+      if (r) return r;
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(KB_EHIP, "autotune timing failed");
+      float m = 0.f;
+      (void)hipEventElapsedTime(&m, e0, e1);
+      ts.push_back(m);
+    }
+    *ms = median(ts);
+    return KB_OK;
+  };
+  kb_tile cur{};
+  double cur_ms = -1.0;
+  auto consider = [&](const kb_tile& t) -> int {
+    double ms = -1.0;
+    const int r = trial(t, &ms);
+    if (r) return r;
+    if (ms >= 0.0 && (cur_ms < 0.0 || ms < cur_ms)) {
+      cur = t;
+      cur_ms = ms;
+    }
+    return KB_OK;
+  };
+  // 1. launch-wide: resident waves per SIMD x staging form
+  for (int wv : {0, 1, 2, 3})
+    for (int st : {KB_STAGING_PREFETCH, KB_STAGING_DIRECT}) {
+      kb_tile t{};
+      t.waves_per_simd = wv;
+      t.staging = st;
+      if ((rc = consider(t))) break;
+    }
+  // 2. the default steps per queue item
+  for (int sp : {1, 2, 8, 16, 32}) {
+    if (rc) break;
+    kb_tile t = cur;
+    t.steps_per_item = sp;
+    rc = consider(t);
+  }
+  if (!rc && cur_ms < 0.0) rc = fail(KB_EHIP, "every autotune candidate failed its parity check");
+  // The block-count classes present among the messages the second pass
+  // hashes (its bucket sizes, read back from the last run's plan).
+  uint32_t present = 0;
+  if (!rc) {
+    Workspace* w = nullptr;
+    rc = get_ws(stream, n, 0, &w);
+    std::vector<uint32_t> fold(kKeyBins);
+    uint32_t ndef_chunks = 0;  // the plan writes the bucket sizes only when some chunk was deferred
+    if (!rc && (hipMemcpyAsync(fold.data(), w->meta + M_FOLD, kKeyBins * 4, hipMemcpyDeviceToHost,
+                               stream) != hipSuccess ||
+                hipMemcpyAsync(&ndef_chunks, w->meta + M_CTL + CTL_NDEF_CHUNKS, 4,
+                               hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess))
+      rc = fail(KB_EHIP, "autotune could not read the bucket sizes");
+    for (uint32_t key = 1; !rc && ndef_chunks && key < kKeyBins; ++key)
+      if (fold[key]) present |= 1u << kb::nb_class_of(key);
+  }
+  // 3. threads per state by class: the five-lane split form for the longest
+  // classes (from class c up) and one lane per message below, for each c
+  // present, and one lane everywhere
+  if (!rc && present) {
+    const kb_tile base = cur;
+    for (int c = KB_NB_CLASSES; c >= 1 && !rc; --c) {  // c = KB_NB_CLASSES: no split class
+      if (c < KB_NB_CLASSES && !((present >> c) & 1u)) continue;
+      kb_tile t = base;
+      for (int k = 0; k < KB_NB_CLASSES; ++k)
+        if ((present >> k) & 1u) t.class_threads[k] = k >= c ? 5 : 1;
+      rc = consider(t);
+    }
+  }
+  // 4. steps per queue item by class, one class at a time
+  for (int c = 0; c < KB_NB_CLASSES && !rc; ++c) {
+    if (!((present >> c) & 1u)) continue;
+    const kb_tile base = cur;
+    for (int sp : {1, 4, 16}) {
+      kb_tile t = base;
+      t.class_steps[c] = sp;
+      if ((rc = consider(t))) break;
+    }
+  }
   cleanup();
+  if (rc) return rc;
+  *best = cur;
+  *best_ms = cur_ms;
   *rejected = nrej;
-  if (best_t < 0.0) return fail(KB_EHIP, "every autotune candidate failed its parity check");
-  *best_ms = best_t;
   return KB_OK;
 }
 

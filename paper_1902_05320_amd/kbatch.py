@@ -31,7 +31,7 @@ NOALLOC_MAX_MSGS = 1 << 20
 EXPORTS = (
     "keccak_batch", "keccak_batch_noalloc", "keccak_batch_mixed", "keccak_batch_xof",
     "keccak_batch_xof_ex", "keccak_batch_ex", "merkle_root", "keccak_autotune",
-    "keccak_graph_create", "keccak_graph_create_counted", "keccak_graph_create_merkle", "keccak_graph_launch",
+    "keccak_tune_store", "keccak_tune_lookup", "keccak_last_tile", "keccak_graph_create", "keccak_graph_create_counted", "keccak_graph_create_merkle", "keccak_graph_launch",
     "keccak_graph_destroy", "keccak_server_create", "keccak_server_submit", "keccak_server_poll",
     "keccak_server_result", "keccak_server_stats", "keccak_server_destroy",
     "keccak_server_last_error", "keccak_tree_workspace_bytes", "keccak_digest_bytes",
@@ -47,9 +47,22 @@ class KbError(RuntimeError):
         self.code = code
 
 
+NB_CLASSES = 8
+STAGING_DEFAULT, STAGING_DIRECT, STAGING_PREFETCH = 0, 1, 2
+
+
 class Tile(ctypes.Structure):
+    """kb_tile: knobs of the persistent form (zero = library default).  The
+    class arrays are indexed by block-count class floor(log2(blocks))."""
     _fields_ = [("block_threads", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("steps_per_item", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("steps_per_item", ctypes.c_int32), ("staging", ctypes.c_int32),
+                ("class_steps", ctypes.c_int32 * NB_CLASSES),
+                ("class_threads", ctypes.c_int32 * NB_CLASSES)]
+
+    def as_dict(self) -> dict:
+        return {"waves_per_simd": self.waves_per_simd, "steps_per_item": self.steps_per_item,
+                "staging": self.staging, "class_steps": list(self.class_steps),
+                "class_threads": list(self.class_threads)}
 
 
 EXECUTOR = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8),
@@ -115,6 +128,10 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_autotune.argtypes = [i32, vp, vp, vp, vp, u64, i32, ctypes.POINTER(Tile),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                     vp]
+    cp = ctypes.c_char_p
+    lib.keccak_tune_store.argtypes = [cp, cp, cp, i32, u64, ctypes.POINTER(Tile), ctypes.c_double]
+    lib.keccak_tune_lookup.argtypes = [cp, cp, cp, i32, u64, ctypes.POINTER(Tile)]
+    lib.keccak_last_tile.argtypes = [ctypes.POINTER(Tile)]
     pp = ctypes.POINTER(ctypes.c_void_p)
     lib.keccak_graph_create.argtypes = [i32, vp, vp, vp, vp, u64, vp, i32, ctypes.POINTER(Tile),
                                         vp, pp]
@@ -140,7 +157,8 @@ def load_library(path: str = LIB_PATH):
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
               "keccak_timing_enable", "keccak_timing_read", "keccak_timing_read_kernel",
               "keccak_probe_valu",
-              "keccak_probe_perm", "keccak_probe_copy", "keccak_autotune", "keccak_graph_create",
+              "keccak_probe_perm", "keccak_probe_copy", "keccak_autotune",
+              "keccak_tune_store", "keccak_tune_lookup", "keccak_last_tile", "keccak_graph_create",
               "keccak_graph_create_counted", "keccak_graph_create_merkle", "keccak_graph_launch",
               "keccak_graph_destroy",
               "keccak_server_create", "keccak_server_submit", "keccak_server_poll",
@@ -379,9 +397,12 @@ def merkle_root(variant, data: torch.Tensor, leaf_size: int, out: torch.Tensor |
 
 
 def autotune(variant, data: torch.Tensor, offsets: torch.Tensor, lengths: torch.Tensor,
-             variants: torch.Tensor | None = None, reps: int = 3, stream=None):
-    """Pick the persistent-form tile for this batch.  variant=-1 with
-    `variants` tunes the mixed form.  Returns (Tile, ms, rejected)."""
+             variants: torch.Tensor | None = None, reps: int = 3, stream=None,
+             cache: str | None = None):
+    """Pick the persistent-form tile for this batch (every candidate checked
+    bit for bit against the plain form first).  variant=-1 with `variants`
+    tunes the mixed form.  With `cache`, the result is merged into that JSON
+    tune cache under this device's key.  Returns (Tile, ms, rejected)."""
     _require_gpu()
     lib = load_library()
     v = -1 if variant == -1 else variant_id(variant)
@@ -394,7 +415,43 @@ def autotune(variant, data: torch.Tensor, offsets: torch.Tensor, lengths: torch.
     _check(lib.keccak_autotune(v, _ptr(variants), _ptr(data), _ptr(offsets), _ptr(lengths), n,
                                int(reps), ctypes.byref(best), ctypes.byref(ms), ctypes.byref(rej),
                                _stream_handle(stream)))
+    if cache is not None:
+        tune_store(cache, v, n, best, ms.value)
     return best, ms.value, rej.value
+
+
+def tune_store(path: str, variant: int, n: int, tile: Tile, ms: float = -1.0,
+               arch: str | None = None, rocm: str | None = None):
+    """Merge `tile` into the JSON tune cache at `path` (key: arch, ROCm,
+    variant (-1 = mixed), block-count classes, batch class of n; arch and
+    rocm default to the current device's)."""
+    lib = load_library()
+    _check(lib.keccak_tune_store(path.encode(), arch.encode() if arch else None,
+                                 rocm.encode() if rocm else None, int(variant), int(n),
+                                 ctypes.byref(tile), float(ms)))
+
+
+def tune_lookup(variant: int, n: int, path: str | None = None, arch: str | None = None,
+                rocm: str | None = None) -> Tile | None:
+    """The cached tile for a batch of n messages of `variant` (-1 = mixed),
+    from `path` or $KBATCH_TUNE; None if no entry matches."""
+    lib = load_library()
+    out = Tile()
+    rc = lib.keccak_tune_lookup(path.encode() if path else None, arch.encode() if arch else None,
+                                rocm.encode() if rocm else None, int(variant), int(n),
+                                ctypes.byref(out))
+    if rc < 0:
+        _check(rc)
+    return out if rc == 1 else None
+
+
+def last_tile() -> tuple[Tile, bool]:
+    """The tile this thread's last batch call ran, and whether it came from
+    the tune cache."""
+    lib = load_library()
+    out = Tile()
+    cached = lib.keccak_last_tile(ctypes.byref(out))
+    return out, bool(cached)
 
 
 class Graph:

@@ -105,7 +105,7 @@ def test_autotune_candidates_pass_parity(kb, o2):
     var = torch.from_numpy(b.variants).cuda()
     _say("autotune mixed")
     tile, ms, rejected = kb.autotune(-1, data, offs, lens, variants=var, reps=2)
-    assert rejected == 0 and ms > 0 and tile.steps_per_item >= 1
+    assert rejected == 0 and ms > 0 and tile.steps_per_item >= 0
     got = kb.keccak_batch_mixed(var, data, offs, lens, tile=tile).cpu().numpy()
     assert np.array_equal(got, o2.sha3_batch_mixed(b.variants, b.data, b.offsets, b.lengths))
     _say("autotune sha3_256")
@@ -113,6 +113,45 @@ def test_autotune_candidates_pass_parity(kb, o2):
     assert rejected == 0
     got = kb.keccak_batch(1, data, offs, lens, tile=tile).cpu().numpy()
     assert np.array_equal(got, o2.sha3_batch(256, b.data, b.offsets, b.lengths))
+
+
+def test_cached_tile_is_chosen_and_matches_oracle(kb, o2, tmp_path, monkeypatch):
+    """A tile stored in the tune cache is the one a batch call runs once
+    KBATCH_TUNE names the file, and its digests equal the oracle's."""
+    import torch
+    b = wl.uneven(20000, 9000, seed=53)
+    data = torch.from_numpy(b.data).cuda()
+    offs = torch.from_numpy(b.offsets).cuda()
+    lens = torch.from_numpy(b.lengths).cuda()
+    var = torch.from_numpy(b.variants).cuda()
+    path = str(tmp_path / "tune.json")
+    _say("autotune mixed into a cache file")
+    tuned, _, rejected = kb.autotune(-1, data, offs, lens, variants=var, reps=1, cache=path)
+    assert rejected == 0
+    assert kb.tune_lookup(-1, b.n, path=path).as_dict() == tuned.as_dict()
+    # a distinctive tile for SHA3-512 over the same batch: direct staging, two
+    # waves per SIMD, every class of 16 or more blocks in the five-lane form
+    t = kb.Tile()
+    t.waves_per_simd, t.steps_per_item, t.staging = 2, 2, kb.STAGING_DIRECT
+    for c in range(kb.NB_CLASSES):
+        t.class_threads[c] = 5 if c >= 4 else 1
+        t.class_steps[c] = 1 + c
+    kb.tune_store(path, 3, b.n, t, 1.0)
+    monkeypatch.setenv("KBATCH_TUNE", path)
+    for v, want in ((3, o2.sha3_batch(512, b.data, b.offsets, b.lengths)),
+                    (-1, o2.sha3_batch_mixed(b.variants, b.data, b.offsets, b.lengths))):
+        _say("cached tile, variant", v)
+        if v == -1:
+            got = kb.keccak_batch_mixed(var, data, offs, lens)
+        else:
+            got = kb.keccak_batch(v, data, offs, lens)
+        used, cached = kb.last_tile()
+        assert cached and used.as_dict() == (t if v == 3 else tuned).as_dict()
+        assert np.array_equal(got.cpu().numpy(), want)
+    monkeypatch.delenv("KBATCH_TUNE")
+    kb.keccak_batch(3, data, offs, lens)
+    used, cached = kb.last_tile()
+    assert not cached and used.waves_per_simd == 0
 
 
 @pytest.mark.parametrize("mode", ["persistent", "plain", "split"])
