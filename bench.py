@@ -249,7 +249,8 @@ def bench_serving(args, kbatch, workloads, torch, dev):
     print("[bench] generating 4 GiB pool and request stream (seed 4)", file=sys.stderr, flush=True)
     pool_np, reqs = workloads.serving_stream(duration + warm, 2000.0, 4 << 30, seed=4)
     pool = torch.from_numpy(pool_np).to(dev)
-    srv = kbatch.Server(pool, max_step_msgs=args.serve_step_msgs, steps_in_flight=args.serve_in_flight)
+    srv = kbatch.Server(pool, max_step_msgs=args.serve_step_msgs, steps_in_flight=args.serve_in_flight,
+                        graphs=not args.serve_eager)
     lat, nbytes, results, sample = [], 0, {}, set(range(0, len(reqs), max(1, len(reqs) // 200)))
     inflight = {}
     t0 = time.perf_counter()
@@ -295,12 +296,14 @@ def bench_serving(args, kbatch, workloads, torch, dev):
     print(json.dumps({"config": {"workload": "serving_poisson_2000rps_1-4096msgs_[0,64KiB]",
                                  "seed": 4, "pool_bytes": 4 << 30, "seconds": duration,
                                  "warmup_s": warm, "max_step_msgs": args.serve_step_msgs,
-                                 "steps_in_flight": args.serve_in_flight},
+                                 "steps_in_flight": args.serve_in_flight,
+                                 "step_form": "eager" if args.serve_eager else "graph"},
                       "requests": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
                       "mean_ms": round(float(lat.mean()), 3),
                       "gb_per_s_hashed": round(nbytes / measured_s / 1e9, 2),
                       "steps": st["steps"], "mean_step_msgs": round(st["messages"] / max(st["steps"], 1)),
+                      "mean_step_ms": round(1e3 * st["step_busy_s"] / max(st["steps"], 1), 3),
                       "gpu_busy_frac": round(st["step_busy_s"] / max(st["span_s"], 1e-9)
                                              / args.serve_in_flight, 3),
                       "alone_vs_mix_equal": f"{ok}/{len(results)}"}), flush=True)
@@ -324,6 +327,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-in-flight", type=int, default=2, help="serving: steps in flight")
     ap.add_argument("--serve-step-msgs", type=int, default=1 << 16, help="serving: messages per step")
+    ap.add_argument("--serve-eager", action="store_true",
+                    help="serving: steps as separate copies and launches instead of one graph replay")
     ap.add_argument("--workload", default="uniform",
                     choices=("uniform", "uneven", "merkle", "serving", "latency"),
                     help="uniform: 2^24 x 64 B SHA3-256 (the reported metric); uneven: 2^20 "

@@ -176,6 +176,10 @@ __device__ __forceinline__ uint64_t blocks_of(uint64_t len, int var) {
   return len / static_cast<uint64_t>(rate_of<V>(var)) + 1u;
 }
 
+// Slot of key k in a partial histogram: the 16 keys of a 64-byte group are
+// 256 words apart, so the most frequent small keys do not share a line.
+__device__ __forceinline__ uint32_t hist_slot(uint32_t k) { return (k & 15u) * (kKeyBins / 16u) + (k >> 4); }
+
 __device__ __forceinline__ uint32_t key_of(uint64_t nb) {
   return nb >= kKeyBins - 1 ? kKeyBins - 1 : static_cast<uint32_t>(nb);
 }
@@ -671,40 +675,30 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
     return;
   }
   // Fold the dirty copies for this thread's 16 consecutive keys lo .. lo + 15
-  // (64-byte aligned) with 16-byte loads, all issued before use, and clear them.
-  static_assert(kRanksPerThread == 16, "four 16-byte loads per copy");
+  // (slots g, g + 256, ..., g = lo / 16: for each i the workgroup's loads
+  // are contiguous) and clear them.
+  static_assert(kRanksPerThread == 16, "a key group of 16 per thread");
   const uint32_t lo = kKeyBins - kRanksPerThread * (t + 1u);
-  uint4 part[kCopies][4];
-#pragma unroll
-  for (uint32_t k = 0; k < kCopies; ++k) {
-    const uint4* src = reinterpret_cast<const uint4*>(meta + M_HIST + k * kKeyBins + lo);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) part[k][v] = (dirty >> k) & 1u ? src[v] : make_uint4(0u, 0u, 0u, 0u);
-  }
+  const uint32_t g = lo >> 4;
   uint32_t byk[kRanksPerThread];  // folded count of key lo + i
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    uint4 s = part[0][v];
+  for (uint32_t i = 0; i < kRanksPerThread; ++i) byk[i] = 0u;
+  for (uint32_t k = 0; k < kCopies; ++k) {
+    if (!((dirty >> k) & 1u)) continue;
+    uint32_t* h = meta + M_HIST + k * kKeyBins + g;
+    uint32_t v[kRanksPerThread];
 #pragma unroll
-    for (uint32_t k = 1; k < kCopies; ++k) {
-      s.x += part[k][v].x;
-      s.y += part[k][v].y;
-      s.z += part[k][v].z;
-      s.w += part[k][v].w;
+    for (uint32_t i = 0; i < kRanksPerThread; ++i) v[i] = h[i * (kKeyBins / 16u)];
+#pragma unroll
+    for (uint32_t i = 0; i < kRanksPerThread; ++i) {
+      byk[i] += v[i];
+      h[i * (kKeyBins / 16u)] = 0u;
     }
-    byk[4 * v] = s.x;
-    byk[4 * v + 1] = s.y;
-    byk[4 * v + 2] = s.z;
-    byk[4 * v + 3] = s.w;
-    reinterpret_cast<uint4*>(meta + M_FOLD + lo)[v] = s;
   }
 #pragma unroll
-  for (uint32_t k = 0; k < kCopies; ++k)
-    if ((dirty >> k) & 1u) {
-      uint4* dst = reinterpret_cast<uint4*>(meta + M_HIST + k * kKeyBins + lo);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dst[v] = make_uint4(0u, 0u, 0u, 0u);
-    }
+  for (int v = 0; v < 4; ++v)
+    reinterpret_cast<uint4*>(meta + M_FOLD + lo)[v] =
+        make_uint4(byk[4 * v], byk[4 * v + 1], byk[4 * v + 2], byk[4 * v + 3]);
   uint32_t cnt[kRanksPerThread], st[kRanksPerThread], c_sum = 0, kmax = 0;
   uint64_t ublocks = 0;  // blocks of this thread's buckets (a key of 4095 counts 4095)
 #pragma unroll
@@ -823,7 +817,7 @@ __device__ __attribute__((noinline)) void defer_chunk(uint32_t* meta, uint32_t* 
     const uint32_t leader = static_cast<uint32_t>(__builtin_ctzll(todo));
     const uint32_t k = __builtin_amdgcn_readlane(key, leader);
     const uint64_t same = __builtin_amdgcn_ballot_w64(valid && key == k) & todo;
-    if (lane == leader) atomicAdd(&hist[k], static_cast<uint32_t>(__builtin_popcountll(same)));
+    if (lane == leader) atomicAdd(&hist[hist_slot(k)], static_cast<uint32_t>(__builtin_popcountll(same)));
     todo &= ~same;
   }
   if (lane == 0) {
