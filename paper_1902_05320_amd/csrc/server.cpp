@@ -262,6 +262,10 @@ void worker_main(kb_server* s) {
 // Build a slot's step graph: the count and descriptor uploads, then the
 // batch captured over the slot's buffers (count read on the device), then the
 // digest download.  The copy sizes are placeholders, set before each replay.
+// The nodes form one chain: with the four uploads as independent branches,
+// the steps of different slots no longer overlapped on the device (each took
+// about twice as long as the same step run eagerly, measured), as if the
+// runtime ran the branches on streams shared by every graph.
 bool build_step_graph(kb_server* s, StepSlot& st) {
   const uint64_t m = s->cfg.max_step_msgs;
   if (keccak_graph_create_counted(-1, st.d_vars, s->cfg.d_pool, st.d_offs, st.d_lens, st.d_count, m,
@@ -270,15 +274,14 @@ bool build_step_graph(kb_server* s, StepSlot& st) {
   if (hipGraphCreate(&st.graph, 0) != hipSuccess) return false;
   if (hipGraphAddMemcpyNode1D(&st.n_count, st.graph, nullptr, 0, st.d_count, st.h_count, 4,
                               hipMemcpyHostToDevice) != hipSuccess ||
-      hipGraphAddMemcpyNode1D(&st.n_offs, st.graph, nullptr, 0, st.d_offs, st.h_offs, 8,
+      hipGraphAddMemcpyNode1D(&st.n_offs, st.graph, &st.n_count, 1, st.d_offs, st.h_offs, 8,
                               hipMemcpyHostToDevice) != hipSuccess ||
-      hipGraphAddMemcpyNode1D(&st.n_lens, st.graph, nullptr, 0, st.d_lens, st.h_lens, 8,
+      hipGraphAddMemcpyNode1D(&st.n_lens, st.graph, &st.n_offs, 1, st.d_lens, st.h_lens, 8,
                               hipMemcpyHostToDevice) != hipSuccess ||
-      hipGraphAddMemcpyNode1D(&st.n_vars, st.graph, nullptr, 0, st.d_vars, st.h_vars, 1,
+      hipGraphAddMemcpyNode1D(&st.n_vars, st.graph, &st.n_lens, 1, st.d_vars, st.h_vars, 1,
                               hipMemcpyHostToDevice) != hipSuccess)
     return false;
-  const hipGraphNode_t uploads[4] = {st.n_count, st.n_offs, st.n_lens, st.n_vars};
-  if (hipGraphAddChildGraphNode(&st.n_batch, st.graph, uploads, 4, kb::native_graph(st.batch)) !=
+  if (hipGraphAddChildGraphNode(&st.n_batch, st.graph, &st.n_vars, 1, kb::native_graph(st.batch)) !=
           hipSuccess ||
       hipGraphAddMemcpyNode1D(&st.n_out, st.graph, &st.n_batch, 1, st.h_out, st.d_out, 64,
                               hipMemcpyDeviceToHost) != hipSuccess)
