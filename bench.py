@@ -202,7 +202,7 @@ def bench_latency(args, kbatch, workloads, torch, dev):
         nb = size // 136 + 1
         row = {"messages": k, "bytes_each": size, "blocks_each": nb}
         ref = None
-        for mode in ("plain", "persistent", "split"):
+        for mode in ("plain", "persistent", "split", "wide"):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch(1, data, offs, lens, out=out, mode=mode,
                                              check_bounds=False)
@@ -223,7 +223,7 @@ def bench_latency(args, kbatch, workloads, torch, dev):
         nb = size // 136 + 1
         row = {"messages": k, "bytes_each": size, "blocks_each": nb, "out_len": 32}
         ref = None
-        for mode in ("plain", "persistent", "split"):
+        for mode in ("plain", "persistent", "split", "wide"):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch_xof(256, data, offs, lens, 32, out=out, mode=mode,
                                                  check_bounds=False)
@@ -334,7 +334,7 @@ def main():
                     help="uniform: 2^24 x 64 B SHA3-256 (the reported metric); uneven: 2^20 "
                          "mixed-variant messages, log-uniform lengths in [0, 16 KiB]; merkle: "
                          "1 GiB in 4 KiB leaves; serving: Poisson request stream; latency: "
-                         "1 to 32768 long messages, one thread vs five lanes per message")
+                         "1 to 32768 long messages, one thread vs five or 32 lanes per message")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -61,10 +61,14 @@ enum kb_mode {
                              paper's "one thread per message", Section 4.1) */
   KB_MODE_PER_BUCKET = 2, /* bucket by block count, one plain launch per bucket (waits on
                              the host for the bucket sizes) */
-  KB_MODE_SPLIT = 3       /* latency form: five lanes of a wave share one state, eight
-                             messages per wave in arrival order (SHA3 variants only; the
-                             serial absorb chain of Section 3.2 runs about twice as fast
-                             per message, at a fraction of the batch throughput) */
+  KB_MODE_SPLIT = 3,      /* latency form: five lanes of a wave share one state, eight
+                             messages per wave in arrival order (the serial absorb chain
+                             of Section 3.2 runs about twice as fast per message, at a
+                             fraction of the batch throughput) */
+  KB_MODE_WIDE = 4        /* wide latency form: one 64-bit state word per lane, 32 lanes
+                             per state, two messages per wave in arrival order (each
+                             lane issues about twenty VALU instructions per round, with
+                             two exchanges through LDS; for the fewest, longest chains) */
 };
 
 /*
@@ -385,7 +389,8 @@ enum kb_kernel {
   KB_KERNEL_SECOND_PASS = 1, /* persistent form: the bucketed pass */
   KB_KERNEL_PLAIN = 2,       /* one thread per message (plain and per-bucket forms) */
   KB_KERNEL_SPLIT = 3,       /* lane-split form */
-  KB_KERNEL_TREE = 4         /* tree mode */
+  KB_KERNEL_TREE = 4,        /* tree mode */
+  KB_KERNEL_WIDE = 5         /* wide lane-split form */
 };
 
 /* keccak_timing_read restricted to the kernels of one kind; KB_EINVAL for

@@ -40,6 +40,7 @@
 #include "kbatch.h"
 #include "sponge_device.h"
 #include "split_device.h"
+#include "wide_device.h"
 
 using kb::kMixed;
 using kb::kShake128;
@@ -358,6 +359,101 @@ __global__ __launch_bounds__(kSplitBlock) void k_split(const uint8_t* __restrict
       continue;
     }
     split_hash<V>(data + offs[i], lens[i], var, o, slot_dw, L);
+  }
+}
+
+// The wide form (one state word per lane, 32 lanes per state): absorb one
+// message into `a` (this lane's word), the next block's word loaded before
+// the current block's permutation.
+template <int V>
+__device__ __forceinline__ void wide_absorb(Lane& a, const uint8_t* msg, uint64_t len, int var,
+                                            const kb::wide::WideLane& L) {
+  namespace wd = kb::wide;
+  using S = SpongeShape<V>;
+  a = Lane{0u, 0u};
+  const int R = rate_of<V>(var);
+  const uint32_t sh = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(msg) & 3u);
+  const uint64_t nb = len / static_cast<uint64_t>(R) + 1u;
+  wd::WordDw d;
+  wd::load_word(d, msg, sh, len, 0, R, L);
+  for (uint64_t b = 0; b < nb; ++b) {
+    const uint64_t boff = b * static_cast<uint64_t>(R);
+    const bool fin = b + 1 == nb;
+    wd::absorb_word(a, d, sh, R, fin, fin ? static_cast<uint32_t>(len - boff) : 0u, S::kPadByte, L);
+    if (!fin) wd::load_word(d, msg, sh, len, boff + R, R, L);
+    wd::wide_permute(a, L);
+  }
+}
+
+// XOF squeeze in the wide form (Section 3.2): each lane writes its word when
+// it lies in the rate, r bits of output per permutation, until out_len bytes
+// are out.  Bytes are stored one by one unless out_len is a multiple of 4
+// and `out` is 4-byte aligned.
+template <int V>
+__device__ __forceinline__ void wide_xof(Lane& a, uint8_t* out, uint64_t out_len,
+                                         const kb::wide::WideLane& L) {
+  constexpr uint32_t R = SpongeShape<V>::kMaxRate;
+  const bool words = (out_len & 3u) == 0 && (reinterpret_cast<uintptr_t>(out) & 3u) == 0;
+  for (uint64_t done = 0;;) {
+    if (8u * L.word < R) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t v = h ? a.hi : a.lo;
+        const uint64_t at = done + 8u * L.word + 4u * h;
+        if (at < out_len) {
+          if (words) {
+            *reinterpret_cast<uint32_t*>(out + at) = v;
+          } else {
+            for (uint32_t q = 0; q < 4u && at + q < out_len; ++q)
+              out[at + q] = static_cast<uint8_t>(v >> (8u * q));
+          }
+        }
+      }
+    }
+    done += R;
+    if (done >= out_len) break;
+    kb::wide::wide_permute(a, L);
+  }
+}
+
+// Wide form: each half of a wave hashes one message at a time, message
+// order[first + p] (or first + p) for p = state, state + states, ...  One
+// wave per workgroup, as in the five-lane form.
+constexpr int kWideBlock = 64;
+constexpr int kWideStates = kWideBlock / kb::wide::kHalfLanes;
+
+template <int V>
+__global__ __launch_bounds__(kWideBlock) void k_wide(const uint8_t* __restrict__ data,
+                                                     const uint64_t* __restrict__ offs,
+                                                     const uint64_t* __restrict__ lens,
+                                                     const uint8_t* __restrict__ vars,
+                                                     const uint32_t* __restrict__ order,
+                                                     uint64_t first, uint64_t count,
+                                                     uint8_t* __restrict__ out, uint64_t stride) {
+  namespace wd = kb::wide;
+  __shared__ __align__(16) uint64_t lds[kWideStates * wd::kAreaSlots];
+  const uint32_t s = threadIdx.x / wd::kHalfLanes, h = threadIdx.x % wd::kHalfLanes;
+  wd::WideLane L;
+  wd::setup(L, h, lds + s * wd::kAreaSlots);
+  const uint64_t states = static_cast<uint64_t>(gridDim.x) * kWideStates;
+  const int slot_dw = V == kMixed ? 16 : V >= kShake128 ? 0 : kb::digest_bytes_of(V) / 4;
+  for (uint64_t p = static_cast<uint64_t>(blockIdx.x) * kWideStates + s; p < count; p += states) {
+    const uint64_t i = order ? order[first + p] : first + p;
+    Lane a;
+    if constexpr (V >= kShake128) {
+      wide_absorb<V>(a, data + offs[i], lens[i], V, L);
+      wide_xof<V>(a, out + i * stride, stride, L);
+      continue;
+    }
+    const int var = V == kMixed ? vars[i] : V;
+    uint32_t* o = reinterpret_cast<uint32_t*>(out + i * stride);
+    if (V == kMixed && var > 3) {  // no such variant: the slot is zeroed
+      wd::store_word(o, Lane{0u, 0u}, 0, slot_dw, L);
+      continue;
+    }
+    wide_absorb<V>(a, data + offs[i], lens[i], var, L);
+    const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
+    wd::store_word(o, a, dw, slot_dw, L);
   }
 }
 
@@ -1394,6 +1490,26 @@ int launch_split(const Batch& b, const uint32_t* order, uint64_t first, uint64_t
   return KB_OK;
 }
 
+template <int V>
+int launch_wide(const Batch& b, const uint32_t* order, uint64_t first, uint64_t count,
+                hipStream_t s) {
+  if (!count) return KB_OK;
+  int dev = 0, cus = 0;
+  KB_HIP(hipGetDevice(&dev));
+  int rc = cu_count(dev, &cus);
+  if (rc) return rc;
+  // one state per message up to 16 waves per CU; beyond that states loop
+  uint64_t grid = (count + kWideStates - 1) / kWideStates;
+  if (grid > static_cast<uint64_t>(16 * cus)) grid = 16 * cus;
+  {
+    TimedLaunch tl(s, KB_KERNEL_WIDE);
+    hipLaunchKernelGGL(k_wide<V>, dim3(static_cast<uint32_t>(grid)), dim3(kWideBlock), 0, s,
+                       b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
+  }
+  KB_HIP(hipGetLastError());
+  return KB_OK;
+}
+
 // Workgroups of `kernel` that fit on the chip at once, capped by the tile's
 // waves per SIMD (a 256-thread workgroup is one wave on each of a CU's four
 // SIMDs).
@@ -1495,6 +1611,7 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Work
               const uint32_t* n_dev) {
   if (mode == KB_MODE_PLAIN) return launch_plain<V>(b, nullptr, 0, b.n, s);
   if (mode == KB_MODE_SPLIT) return launch_split<V>(b, nullptr, 0, b.n, s);
+  if (mode == KB_MODE_WIDE) return launch_wide<V>(b, nullptr, 0, b.n, s);
   if (b.n >= 0xFFFFFFFFull) return launch_plain<V>(b, nullptr, 0, b.n, s);  // 32-bit order[]
   Workspace* w = own;
   int rc = own ? KB_OK : get_ws(s, b.n, 0, &w);
@@ -1520,7 +1637,7 @@ int check_batch(const Batch& b, int mode) {
   if (b.variant != kMixed && b.variant != kShake128 && b.variant != kShake256 &&
       (b.variant < 0 || b.variant > 3))
     return fail(KB_EINVAL, "variant %d is not a SHA-3 variant (0..3)", b.variant);
-  if (mode < KB_MODE_PERSISTENT || mode > KB_MODE_SPLIT)
+  if (mode < KB_MODE_PERSISTENT || mode > KB_MODE_WIDE)
     return fail(KB_EINVAL, "unknown scheduling mode %d", mode);
   if (b.n == 0) return KB_OK;
   if (!b.data || !b.offs || !b.lens || !b.out || (b.variant == kMixed && !b.vars))
@@ -2217,7 +2334,7 @@ int keccak_timing_read(double* total_ms, uint64_t* launches) {
 }
 
 int keccak_timing_read_kernel(int kind, double* total_ms, uint64_t* launches) {
-  if (kind < KB_KERNEL_FIRST_PASS || kind > KB_KERNEL_TREE) {
+  if (kind < KB_KERNEL_FIRST_PASS || kind > KB_KERNEL_WIDE) {
     g_err.clear();
     return fail(KB_EINVAL, "unknown kernel kind %d", kind);
   }

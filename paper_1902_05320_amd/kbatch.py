@@ -22,7 +22,7 @@ DIGEST_BYTES = (28, 32, 48, 64)
 RATE_BYTES = (144, 136, 104, 72)
 
 MODE_PERSISTENT, MODE_PLAIN, MODE_PER_BUCKET, MODE_SPLIT = 0, 1, 2, 3
-MODES = {"persistent": 0, "plain": 1, "per_bucket": 2, "split": 3}
+MODES = {"persistent": 0, "plain": 1, "per_bucket": 2, "split": 3, "wide": 4}
 
 KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
 NOALLOC_MAX_MSGS = 1 << 20
@@ -223,7 +223,7 @@ def keccak_batch(variant, data: torch.Tensor, offsets: torch.Tensor, lengths: to
                  out: torch.Tensor | None = None, stream=None, mode="persistent",
                  tile: Tile | None = None, check_bounds: bool = True) -> torch.Tensor:
     """SHA-3 digests of every (offset, length) slice of `data`; returns
-    uint8[n, D] on the device.  `mode` is persistent, plain, per_bucket or split."""
+    uint8[n, D] on the device.  `mode` is persistent, plain, per_bucket, split or wide."""
     _require_gpu()
     lib = load_library()
     v = variant_id(variant)
@@ -326,7 +326,7 @@ def keccak_batch_xof(security: int, data: torch.Tensor, offsets: torch.Tensor,
                      mode: str = "persistent") -> torch.Tensor:
     """SHAKE128/256 of every slice, out_len bytes each; returns uint8[n, out_len].
 
-    mode: "persistent" (default), "plain", "per_bucket" or "split"."""
+    mode: "persistent" (default), "plain", "per_bucket", "split" or "wide"."""
     _require_gpu()
     lib = load_library()
     if security not in (128, 256):
@@ -641,7 +641,7 @@ def timing_enable(on: bool = True):
     _check(load_library().keccak_timing_enable(1 if on else 0))
 
 
-KERNELS = {"first_pass": 0, "second_pass": 1, "plain": 2, "split": 3, "tree": 4}
+KERNELS = {"first_pass": 0, "second_pass": 1, "plain": 2, "split": 3, "tree": 4, "wide": 5}
 
 
 def timing_read(kernel: str | None = None) -> tuple[float, int]:
