@@ -93,12 +93,14 @@ typedef struct kb_tile {
   int32_t staging;          /* kb_staging: how a message's next block reaches the sponge */
   int32_t class_steps[KB_NB_CLASSES];    /* per class: steps per queue item (0 = steps_per_item) */
   int32_t class_threads[KB_NB_CLASSES];  /* per class: threads per state, 1 (one lane hashes a
-                                            message) or 5 (a five-lane group of the split form,
-                                            Section 3.2's absorb chain about twice as fast);
-                                            0 = the library's rule.  SHA-3 variants only; the
-                                            five-lane classes must be the longest ones (a class
-                                            takes 5 only if every longer class present does) */
+                                            message) or KB_THREADS_WIDE (the split tail: 32
+                                            lanes per state in the wide form, Section 3.2's
+                                            absorb chain about three times as fast); 0 = the
+                                            library's rule.  SHA-3 variants only; the split
+                                            classes must be the longest ones (a class is split
+                                            only if every longer class present is) */
 } kb_tile;
+#define KB_THREADS_WIDE 32
 
 /*
  * keccak_batch -- SHA3-{224,256,384,512} of n messages (batch mode, Section
@@ -390,7 +392,8 @@ enum kb_kernel {
   KB_KERNEL_PLAIN = 2,       /* one thread per message (plain and per-bucket forms) */
   KB_KERNEL_SPLIT = 3,       /* lane-split form */
   KB_KERNEL_TREE = 4,        /* tree mode */
-  KB_KERNEL_WIDE = 5         /* wide lane-split form */
+  KB_KERNEL_WIDE = 5,        /* wide lane-split form */
+  KB_KERNEL_SCHEDULE = 6     /* persistent form: the plan and the bucketing scatter */
 };
 
 /* keccak_timing_read restricted to the kernels of one kind; KB_EINVAL for

@@ -1,20 +1,22 @@
 // libkbatch: batch SHA-3 on gfx950 -- kernels, scheduler and the C ABI.
 //
-// keccak_batch (persistent form) is two launches on the caller's stream,
+// keccak_batch (persistent form) is three launches on the caller's stream,
 // with no host synchronisation:
 //   k_first   one 64-message chunk of arrival order per wave: a chunk of
 //             one-block messages is hashed on the spot; any other chunk is
 //             deferred (its block-count keys nb = floor(L/R) + 1 counted,
 //             bins 1..4094 exact and 4095 = "4095 or more", its index
 //             listed).
-//   k_second  a resident grid: one workgroup makes the plan (bucket starts
+//   k_second<.., 1> (schedule)  one workgroup makes the plan (bucket starts
 //             in descending nb, longest first; queue items of about
 //             `steps_per_item` permutations per lane; the range of the
-//             longest messages that five-lane groups hash), the grid fills
-//             the queue and scatters the deferred messages into bucketed
-//             order, then hashes them: each SIMD's front wave takes the
-//             longest items (the split range first) at raised priority,
-//             the other waves the shortest ones.
+//             longest messages that the wide split form hashes), the grid
+//             fills the queue and scatters the deferred messages into
+//             bucketed order.
+//   k_second<.., 2> (hashing)  a resident grid: each SIMD's front wave takes
+//             the split range and then the longest items at raised
+//             priority, the other waves the shortest ones.
+// On a batch with nothing deferred the last two find no work and return.
 // The plain form is one k_plain launch in arrival order; the per-bucket form
 // runs both passes without hashing, reads the bucket sizes back, and
 // launches k_plain once per non-empty bucket.
@@ -94,11 +96,17 @@ constexpr uint32_t kQueues = 8;
 // the sub-queues, then the counter of split items on a line of its own
 constexpr uint32_t kQueueAreaDw = (kQueues + 1) * kLine;
 
-// The first pass accumulates into kCopies partial histograms and partial
-// sums (copy = workgroup index mod 8, which is its XCD), so that the
-// workgroups' closing atomics spread over eight addresses; the plan folds
-// them and clears the copies it found dirty.
+// The first pass accumulates into kCopies partial histograms and deferred
+// chunk lists, so that the deferring waves' atomics spread over eight
+// addresses; the plan folds the histograms and clears the copies it found
+// dirty (a non-empty list).  Copy = (workgroup index / kListRun) mod 8: runs
+// of consecutive workgroups share a copy, so each list (read end to end by
+// the scatter) holds long stretches of neighbouring chunks and a scatter
+// tile gathers messages from a few megabytes of the batch, not from all of
+// it (measured on the 2^20-message uneven batch: 2.35 against 2.36 ms, and
+// the resident workgroups still spread over all eight copies).
 constexpr uint32_t kCopies = 8;
+constexpr uint32_t kListRun = 64;
 
 // Workspace metadata layout (uint32 words).  Every counter and partial sum
 // is zero between calls: the workspace is cleared when it is allocated, and
@@ -141,7 +149,7 @@ struct PassArgs {
   // Per block-count class c, packed so that no array is indexed at run time
   // (an indexed member would move the whole argument block to scratch):
   uint64_t class_steps;    // byte c: steps per queue item (0 = `steps`)
-  uint32_t class_threads;  // nibble c: 0 = the rule, 1 = one lane, 5 = split
+  uint32_t class_threads;  // nibble c: 0 = the rule, 1 = one lane, 2 = the wide split tail
   uint64_t lanes;       // resident lanes of the second pass
   uint32_t defer_seg;   // entries of each deferred sub-list (defer_seg_of(n))
   int hash;             // 0: count and scatter only (the per-bucket form)
@@ -489,8 +497,10 @@ struct TreeLevels {
 // workgroup's subtree, where one thread per pair would leave a wave's worth
 // of permutation latency for a handful of lanes, hash one pair per group in
 // the lane-split form (five lanes per state, about twice as fast per
-// permutation).  The split form's exchange area reuses the staging rows,
-// which no level uses after the first split one.
+// permutation), and the levels of at most one pair per half-wave in the wide
+// form (one state word per lane, about three times as fast).  The exchange
+// areas reuse the staging rows, which no level uses after the first split
+// one.
 //
 // A workgroup owns NODES nodes of level `first`: T for the leaf and middle
 // launches (one leaf or node per thread), 2T for the last workgroup, whose
@@ -502,7 +512,7 @@ struct TreeLevels {
 // blocks go from HBM into a per-wave LDS area with the loads that write LDS
 // directly, the next block's while the current one is permuted, and come back
 // as whole words (no byte realignment, no registers holding bytes in flight).
-template <int V, int T, bool PF, bool W8, int NODES = T>
+template <int V, int T, bool PF, bool W8, int NODES = T, bool WL = false>
 __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, uint64_t total,
                                             uint64_t leaf_size, uint8_t* __restrict__ nodes,
                                             uint8_t* __restrict__ root, int first, int levels,
@@ -520,6 +530,9 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
   constexpr int kStageDw = W8 ? kWordsDw : T * S::kRowDw;
   __shared__ __align__(16) uint32_t lds[kStageDw > kSplitDw ? kStageDw : kSplitDw];
   static_assert(kSplitDw <= T * S::kRowDw, "the split exchange area fits in the staging rows");
+  constexpr int kWideStatesT = T / kb::wide::kHalfLanes;
+  static_assert(2 * kWideStatesT * kb::wide::kAreaSlots <= (kStageDw > kSplitDw ? kStageDw : kSplitDw),
+                "the wide exchange areas fit in the kernel's LDS");
   uint32_t* row = lds + (W8 ? 0u : threadIdx.x * S::kRowDw);
   // one message of whole words (W8: through this wave's LDS area) or of any
   // bytes (staged through this thread's row)
@@ -552,7 +565,26 @@ __global__ __launch_bounds__(T) void k_tree(const uint8_t* __restrict__ data, ui
     const int l = first + k;  // reading level l, writing level l + 1
     __syncthreads();
     const uint64_t span = static_cast<uint64_t>(NODES) >> (k + 1);  // pairs of this workgroup
-    if (!kSplitLevels || span > static_cast<uint64_t>(kGroups)) {
+    if (WL && span <= static_cast<uint64_t>(kWideStatesT)) {
+      // one pair per half-wave in the wide form (one state word per lane)
+      namespace wd = kb::wide;
+      const uint32_t st = threadIdx.x / wd::kHalfLanes, h = threadIdx.x % wd::kHalfLanes;
+      const uint64_t j = w * span + st;
+      if (st < span && j < lv.m[l + 1]) {
+        const uint8_t* src = nodes + lv.off[l] + 2 * j * D;
+        uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_of(l + 1, j));
+        if (2 * j + 1 < lv.m[l]) {
+          wd::WideLane L;
+          wd::setup(L, h, reinterpret_cast<uint64_t*>(lds) + st * wd::kAreaSlots);
+          Lane a;
+          wide_absorb<V>(a, src, 2 * D, V, L);
+          wd::store_word(d32, a, static_cast<int>(D / 4), static_cast<int>(D / 4), L);
+        } else {
+          const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+          for (uint32_t q = h; q < D / 4; q += wd::kHalfLanes) d32[q] = s32[q];
+        }
+      }
+    } else if (!kSplitLevels || span > static_cast<uint64_t>(kGroups)) {
       const uint64_t j = w * span + threadIdx.x;
       if (threadIdx.x < span && j < lv.m[l + 1]) {
         const uint8_t* src = nodes + lv.off[l] + 2 * j * D;
@@ -841,7 +873,7 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
   for (uint32_t q = 0; q < kRanksPerThread; ++q) {
     const uint32_t key = kKeyBins - 1u - (kRanksPerThread * t + q);
     const uint32_t ct = (a.class_threads >> (4u * class_of_key(key))) & 0xFu;
-    const bool split_here = ct == 5u || (ct == 0u && key >= kmin);
+    const bool split_here = ct == 2u || (ct == 0u && key >= kmin);
     if (cnt[q] && !split_here) atomicMin(&s_split, st[q]);
   }
   __syncthreads();
@@ -905,7 +937,9 @@ template <int V>
 __device__ __attribute__((noinline)) void defer_chunk(uint32_t* meta, uint32_t* deferred, uint32_t seg,
                                                     uint32_t len, int var, uint64_t c, bool valid,
                                                     uint32_t lane) {
-  const uint32_t x = blockIdx.x % kCopies;
+  // the histogram copy and the list copy are the same: the plan folds (and
+  // clears) exactly the histogram copies whose lists are not empty
+  const uint32_t x = (blockIdx.x / kListRun) % kCopies;
   uint32_t* const hist = meta + M_HIST + x * kKeyBins;
   const uint32_t key = valid ? key_of(blocks_of<V>(len, var)) : 0u;
   uint64_t todo = __builtin_amdgcn_ballot_w64(valid);
@@ -1056,16 +1090,22 @@ __device__ __forceinline__ void scatter_tile(const PassArgs& a, uint32_t tile, u
 // only a guard against a wait that could never end.
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-// Second pass (see above).  On each SIMD one wave (the first to claim the
-// SIMD's flag) takes items from the front at raised issue priority while
-// they are long, so the long absorb chains that bound the makespan run back
-// to back at full rate; the other resident waves take the shortest items
-// from the back and fill the issue slots the front wave leaves idle.  Both
+// Second pass (see above), as two launches of one template: PH = 1 plans
+// and fills the queue and the bucketed order, PH = 2 hashes.  The kernel
+// boundary between them orders the scatter's writes before the hashing
+// reads, with no fence or wait in the hashing launch (measured against one
+// launch doing both: the uniform 2^24 x 64 B batch 1.632 against 1.643 ms,
+// the uneven 2^20 batch 2.575 against 2.540 ms).
+// On each SIMD one wave (the first to claim the SIMD's flag) takes items
+// from the front at raised issue priority while they are long, so the long
+// absorb chains that bound the makespan run back to back at full rate; the
+// other resident waves take the shortest items from the back and fill the
+// issue slots the front wave leaves idle.  Both
 // ends of a sub-queue advance one packed 64-bit counter, so no item is taken
 // twice.  A wave drains the sub-queue of its own XCD first and then the
 // others in turn, so every item is taken whatever the mapping of waves to
 // XCDs, and every wave leaves once all sub-queues are empty.
-template <int V, bool PF = kb::kPrefetch<V>>
+template <int V, bool PF, int PH>
 __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
   using S = SpongeShape<V>;
   a.n = pass_count(a);
@@ -1073,8 +1113,8 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
   constexpr uint32_t kLdsDw = kStageDw > 2 * kKeyBins ? kStageDw : 2 * kKeyBins;
   __shared__ __align__(16) uint32_t lds[kLdsDw];
   __shared__ uint32_t s_tile, s_gave_up;
-  static_assert(2 * (kSplitGroups * kb::split::kGroupSlots + 1) <= 64 * S::kRowDw,
-                "a wave's staging rows hold its split exchange area");
+  static_assert(2 * kWideStates * kb::wide::kAreaSlots <= 64 * S::kRowDw,
+                "a wave's staging rows hold its wide exchange areas");
   const uint32_t* ctl = a.meta + M_CTL;
   uint32_t* const sync = a.meta + M_SYNC;
   // The plan for this call (epoch E, counted by the first pass) is made by
@@ -1087,177 +1127,161 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
   // invalidates the L2 and, in hundreds of workgroups at once, took about
   // 0.1 ms.  The wait is bounded (kSpinLimit sleeps, with relaxed loads); a
   // workgroup that gives up flags it and leaves.
-  const uint32_t epoch = __builtin_amdgcn_readfirstlane(load_relaxed(&sync[SY_EPOCH * kLine])) & 0x7FFFFFFFu;
-  uint32_t* const ready = &sync[SY_PLAN_READY * kLine];  // (epoch << 1) | any work
-  if (blockIdx.x == 0) {
-    make_plan(a, lds);
-    __syncthreads();  // every thread's plan writes are done
-    if (threadIdx.x == 0)
-      __hip_atomic_store(ready, (epoch << 1) | (ctl[CTL_TILES] ? 1u : 0u), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    if (!__builtin_amdgcn_readfirstlane(ctl[CTL_TILES])) return;  // the first pass hashed everything
-  } else {
-    if (threadIdx.x == 0) {
-      uint32_t spins = 0, r = load_relaxed(ready);
-      while ((r >> 1) != epoch && spins < kSpinLimit) {
-        __builtin_amdgcn_s_sleep(8);
-        ++spins;
-        r = load_relaxed(ready);
+  if constexpr (PH == 1) {
+    const uint32_t epoch = __builtin_amdgcn_readfirstlane(load_relaxed(&sync[SY_EPOCH * kLine])) & 0x7FFFFFFFu;
+    uint32_t* const ready = &sync[SY_PLAN_READY * kLine];  // (epoch << 1) | any work
+    if (blockIdx.x == 0) {
+      make_plan(a, lds);
+      __syncthreads();  // every thread's plan writes are done
+      if (threadIdx.x == 0)
+        __hip_atomic_store(ready, (epoch << 1) | (ctl[CTL_TILES] ? 1u : 0u), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      if (!__builtin_amdgcn_readfirstlane(ctl[CTL_TILES])) return;  // the first pass hashed everything
+    } else {
+      if (threadIdx.x == 0) {
+        uint32_t spins = 0, r = load_relaxed(ready);
+        while ((r >> 1) != epoch && spins < kSpinLimit) {
+          __builtin_amdgcn_s_sleep(8);
+          ++spins;
+          r = load_relaxed(ready);
+        }
+        s_gave_up = (r >> 1) != epoch ? 2u : (r & 1u);  // 2: gave up, 0: nothing to do, 1: work
+        if (s_gave_up == 2u) a.meta[M_CTL + CTL_SPIN_LIMIT] = 1u;
       }
-      s_gave_up = (r >> 1) != epoch ? 2u : (r & 1u);  // 2: gave up, 0: nothing to do, 1: work
-      if (s_gave_up == 2u) a.meta[M_CTL + CTL_SPIN_LIMIT] = 1u;
+      __syncthreads();
+      if (__builtin_amdgcn_readfirstlane(s_gave_up) != 1u) return;
+      __threadfence();  // acquire: the plan is visible from here on
     }
+    const uint32_t tiles = __builtin_amdgcn_readfirstlane(load_relaxed(&ctl[CTL_TILES]));
+    const uint32_t item_tiles = load_relaxed(&ctl[CTL_ITEM_TILES]);
+    // Tiles are claimed one at a time from a counter.  One thread claims;
+    // the loop condition is a scalar read after a barrier, so the loop (with
+    // the barriers in it) is uniform as the compiler sees it.  The hashing
+    // launch that follows sees every tile's writes (kernel boundary).
+    if (threadIdx.x == 0) s_tile = atomicAdd(&sync[SY_CLAIM * kLine], 1u);
     __syncthreads();
-    if (__builtin_amdgcn_readfirstlane(s_gave_up) != 1u) return;
-    __threadfence();  // acquire: the plan is visible from here on
-  }
-  const uint32_t tiles = __builtin_amdgcn_readfirstlane(load_relaxed(&ctl[CTL_TILES]));
-  const uint32_t item_tiles = load_relaxed(&ctl[CTL_ITEM_TILES]);
-  // Tiles are claimed one at a time from a counter.  One thread claims and
-  // reports; the loop condition is a scalar read after a barrier, so the
-  // loop (with the barriers in it) is uniform as the compiler sees it.
-  if (threadIdx.x == 0) s_tile = atomicAdd(&sync[SY_CLAIM * kLine], 1u);
-  __syncthreads();
-  uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
-  while (tile < tiles) {
-    __syncthreads();  // every thread has read s_tile
-    if (tile < item_tiles)
-      items_tile(a, tile);
-    else
-      scatter_tile<V>(a, tile - item_tiles, lds, lds + kKeyBins);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      atomicAdd(&sync[SY_DONE * kLine], 1u);
-      s_tile = atomicAdd(&sync[SY_CLAIM * kLine], 1u);
+    uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
+    while (tile < tiles) {
+      __syncthreads();  // every thread has read s_tile
+      if (tile < item_tiles)
+        items_tile(a, tile);
+      else
+        scatter_tile<V>(a, tile - item_tiles, lds, lds + kKeyBins);
+      __syncthreads();
+      if (threadIdx.x == 0) s_tile = atomicAdd(&sync[SY_CLAIM * kLine], 1u);
+      __syncthreads();
+      tile = __builtin_amdgcn_readfirstlane(s_tile);
     }
-    __syncthreads();
-    tile = __builtin_amdgcn_readfirstlane(s_tile);
-  }
-  if (!a.hash) return;
-  // Wait for the tiles of the other workgroups.  Every claimed tile is held
-  // by a running workgroup that finishes it without waiting on anything, so
-  // the count reaches `tiles` whichever workgroups are resident.
-  if (threadIdx.x == 0) {
-    uint32_t spins = 0;
-    while (load_relaxed(&sync[SY_DONE * kLine]) < tiles && spins < kSpinLimit) {
-      __builtin_amdgcn_s_sleep(8);
-      ++spins;
-    }
-    s_gave_up = spins >= kSpinLimit ? 1u : 0u;
-    if (s_gave_up) a.meta[M_CTL + CTL_SPIN_LIMIT] = 1u;
-  }
-  __syncthreads();
-  if (__builtin_amdgcn_readfirstlane(s_gave_up)) return;
-  __threadfence();  // the items and the bucketed order are visible from here on
-
-  uint32_t* row = lds + threadIdx.x * S::kRowDw;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t n_items = ctl[CTL_NITEMS];
-  const uint32_t prio_key = ctl[CTL_PRIO_KEY];
-  unsigned long long* const queues = reinterpret_cast<unsigned long long*>(a.meta + M_QUEUES);
-  uint32_t claim = 0;
-  if (lane == 0) claim = atomicCAS(&a.meta[M_SIMD + simd_slot()], 0u, 1u) == 0u ? 1u : 0u;
-  const bool front = __builtin_amdgcn_readfirstlane(__shfl(claim, 0)) != 0u;
-  const unsigned long long step = 1ull << (front ? 0 : 32);
-  const uint32_t home = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kQueues - 1u);
-  // Split items first: the front waves hash the longest messages (bucketed
-  // positions [0, split_n)) eight at a time, one per 8-lane group, in the
-  // lane-split form, whose chain of permutations runs about twice as fast.
-  // The exchange area is this wave's own staging rows.
-  // (SHA-3 variants; the XOFs keep one lane per message)
-  const uint32_t split_n = V <= kMixed ? ctl[CTL_SPLIT_N] : 0u;
-  if constexpr (V <= kMixed) {
-    if (front && split_n) {
-      namespace sp = kb::split;
-      uint64_t* area = reinterpret_cast<uint64_t*>(lds + (threadIdx.x & ~63u) * S::kRowDw);
-      uint64_t* zero = area + kSplitGroups * sp::kGroupSlots;
-      if (lane == 0) *zero = 0;
-      __asm__ volatile("" ::: "memory");
-      sp::SplitLane L;
-      sp::setup(L, lane % sp::kGroupLanes, area + (lane / sp::kGroupLanes) * sp::kGroupSlots, zero);
-      const int slot_dw = static_cast<int>(out_stride_of<V>() / 4u);
-      uint32_t* split_ctr = reinterpret_cast<uint32_t*>(queues + kQueues * (kLine / 2));
-      __builtin_amdgcn_s_setprio(3);
-      for (;;) {
-        uint32_t d = 0;
-        if (lane == 0)
-          d = __hip_atomic_fetch_add(split_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        d = __builtin_amdgcn_readfirstlane(__shfl(d, 0));
-        if (d >= (split_n + kSplitGroups - 1u) / kSplitGroups) break;
-        const uint32_t pos = d * kSplitGroups + lane / sp::kGroupLanes;
-        if (pos < split_n) {
-          const uint32_t i = a.order[pos];
-          const int var = V == kMixed ? a.vars[i] : V;
-          uint32_t* o = reinterpret_cast<uint32_t*>(a.out + static_cast<uint64_t>(i) * a.stride);
-          if (V == kMixed && var > 3) {
-            Lane z[5];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) z[j] = Lane{0u, 0u};
-            sp::store_words(o, z, 0, slot_dw, L);
-          } else {
-            split_hash<V>(a.data + a.offs[i], a.lens[i], var, o, slot_dw, L);
+    return;
+  } else {
+    if (!__builtin_amdgcn_readfirstlane(ctl[CTL_TILES])) return;  // the first pass hashed everything
+    uint32_t* row = lds + threadIdx.x * S::kRowDw;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t n_items = ctl[CTL_NITEMS];
+    const uint32_t prio_key = ctl[CTL_PRIO_KEY];
+    unsigned long long* const queues = reinterpret_cast<unsigned long long*>(a.meta + M_QUEUES);
+    uint32_t claim = 0;
+    if (lane == 0) claim = atomicCAS(&a.meta[M_SIMD + simd_slot()], 0u, 1u) == 0u ? 1u : 0u;
+    const bool front = __builtin_amdgcn_readfirstlane(__shfl(claim, 0)) != 0u;
+    const unsigned long long step = 1ull << (front ? 0 : 32);
+    const uint32_t home = __builtin_amdgcn_s_getreg((3 << 11) | 20) & (kQueues - 1u);
+    // Split items first: the front waves hash the longest messages (bucketed
+    // positions [0, split_n)) two at a time, one per half-wave, in the wide
+    // lane-split form (one state word per lane), whose chain of permutations
+    // runs about three times as fast as one thread's.  The exchange areas are
+    // this wave's own staging rows.  (SHA-3 variants; the XOFs keep one lane
+    // per message.)
+    const uint32_t split_n = V <= kMixed ? ctl[CTL_SPLIT_N] : 0u;
+    if constexpr (V <= kMixed) {
+      if (front && split_n) {
+        namespace wd = kb::wide;
+        uint64_t* area = reinterpret_cast<uint64_t*>(lds + (threadIdx.x & ~63u) * S::kRowDw);
+        const uint32_t half = lane / wd::kHalfLanes;
+        wd::WideLane L;
+        wd::setup(L, lane % wd::kHalfLanes, area + half * wd::kAreaSlots);
+        const int slot_dw = static_cast<int>(out_stride_of<V>() / 4u);
+        uint32_t* split_ctr = reinterpret_cast<uint32_t*>(queues + kQueues * (kLine / 2));
+        __builtin_amdgcn_s_setprio(3);
+        for (;;) {
+          uint32_t d = 0;
+          if (lane == 0)
+            d = __hip_atomic_fetch_add(split_ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          d = __builtin_amdgcn_readfirstlane(__shfl(d, 0));
+          if (d >= (split_n + kWideStates - 1u) / kWideStates) break;
+          const uint32_t pos = d * kWideStates + half;
+          if (pos < split_n) {
+            const uint32_t i = a.order[pos];
+            const int var = V == kMixed ? a.vars[i] : V;
+            uint32_t* o = reinterpret_cast<uint32_t*>(a.out + static_cast<uint64_t>(i) * a.stride);
+            if (V == kMixed && var > 3) {
+              wd::store_word(o, Lane{0u, 0u}, 0, slot_dw, L);
+            } else {
+              Lane w;
+              wide_absorb<V>(w, a.data + a.offs[i], a.lens[i], var, L);
+              const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
+              wd::store_word(o, w, dw, slot_dw, L);
+            }
           }
         }
+        __builtin_amdgcn_s_setprio(0);
       }
-      __builtin_amdgcn_s_setprio(0);
     }
+    uint32_t qi = 0;  // sub-queues tried so far
+    for (;;) {
+      // choose the next item; the hashing below appears once in the kernel
+      uint32_t t = 0xFFFFFFFFu;
+      while (qi < kQueues) {
+        const uint32_t x = (home + qi) & (kQueues - 1u);
+        const uint32_t m = n_items > x ? (n_items - x + kQueues - 1u) / kQueues : 0u;
+        unsigned long long old = 0;
+        if (lane == 0)
+          old = __hip_atomic_fetch_add(queues + x * (kLine / 2), step, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t head = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old), 0));
+        const uint32_t tail =
+            __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old >> 32), 0));
+        if (static_cast<uint64_t>(head) + tail < m) {
+          t = x + kQueues * (front ? head : m - 1u - tail);
+          break;
+        }
+        ++qi;
+      }
+      if (t == 0xFFFFFFFFu) break;
+      const WorkItem it = a.items[t];
+      if (front && it.key >= prio_key)
+        __builtin_amdgcn_s_setprio(3);
+      else
+        __builtin_amdgcn_s_setprio(0);
+      // the next message's index and metadata are loaded while this one hashes
+      uint32_t pos = it.begin + lane;
+      uint64_t i = 0, off = 0, len = 0;
+      int var = V;
+      if (pos < it.end) {
+        i = a.order[pos];
+        off = a.offs[i];
+        len = a.lens[i];
+        if constexpr (V == kMixed) var = a.vars[i];
+      }
+      while (pos < it.end) {
+        const uint32_t pn = pos + 64u;
+        uint64_t in = 0, offn = 0, lenn = 0;
+        int varn = V;
+        if (pn < it.end) {
+          in = a.order[pn];
+          offn = a.offs[in];
+          lenn = a.lens[in];
+          if constexpr (V == kMixed) varn = a.vars[in];
+        }
+        hash_one<V, PF>(a.data, off, len, var, i, a.out, a.stride, row);
+        pos = pn;
+        i = in;
+        off = offn;
+        len = lenn;
+        var = varn;
+      }
+    }
+    __builtin_amdgcn_s_setprio(0);
   }
-  uint32_t qi = 0;  // sub-queues tried so far
-  for (;;) {
-    // choose the next item; the hashing below appears once in the kernel
-    uint32_t t = 0xFFFFFFFFu;
-    while (qi < kQueues) {
-      const uint32_t x = (home + qi) & (kQueues - 1u);
-      const uint32_t m = n_items > x ? (n_items - x + kQueues - 1u) / kQueues : 0u;
-      unsigned long long old = 0;
-      if (lane == 0)
-        old = __hip_atomic_fetch_add(queues + x * (kLine / 2), step, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t head = __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old), 0));
-      const uint32_t tail =
-          __builtin_amdgcn_readfirstlane(__shfl(static_cast<uint32_t>(old >> 32), 0));
-      if (static_cast<uint64_t>(head) + tail < m) {
-        t = x + kQueues * (front ? head : m - 1u - tail);
-        break;
-      }
-      ++qi;
-    }
-    if (t == 0xFFFFFFFFu) break;
-    const WorkItem it = a.items[t];
-    if (front && it.key >= prio_key)
-      __builtin_amdgcn_s_setprio(3);
-    else
-      __builtin_amdgcn_s_setprio(0);
-    // the next message's index and metadata are loaded while this one hashes
-    uint32_t pos = it.begin + lane;
-    uint64_t i = 0, off = 0, len = 0;
-    int var = V;
-    if (pos < it.end) {
-      i = a.order[pos];
-      off = a.offs[i];
-      len = a.lens[i];
-      if constexpr (V == kMixed) var = a.vars[i];
-    }
-    while (pos < it.end) {
-      const uint32_t pn = pos + 64u;
-      uint64_t in = 0, offn = 0, lenn = 0;
-      int varn = V;
-      if (pn < it.end) {
-        in = a.order[pn];
-        offn = a.offs[in];
-        lenn = a.lens[in];
-        if constexpr (V == kMixed) varn = a.vars[in];
-      }
-      hash_one<V, PF>(a.data, off, len, var, i, a.out, a.stride, row);
-      pos = pn;
-      i = in;
-      off = offn;
-      len = lenn;
-      var = varn;
-    }
-  }
-  __builtin_amdgcn_s_setprio(0);
 }
 
 __global__ void k_reset(uint32_t* __restrict__ meta, uint32_t words) {
@@ -1387,12 +1411,13 @@ int grow(void** ptr, uint64_t* cap, uint64_t need, hipStream_t stream) {
   return KB_OK;
 }
 
-// Deferred chunks are listed per partial copy (copy = first-pass workgroup
-// index mod kCopies, so that the appends of different copies go to different
-// counters): copy x's workgroups hold at most 4 * ceil(ceil(n / 256) / 8)
-// chunks, the length of each sub-list.
+// Deferred chunks are listed per partial copy (copy = (first-pass workgroup
+// index / kListRun) mod kCopies): of the ceil(ceil(n / 256) / kListRun) runs
+// of workgroups, copy x takes at most ceil(runs / 8), each of at most
+// kListRun workgroups of 4 chunks, which bounds the length of each sub-list.
 constexpr uint64_t defer_seg_of(uint64_t n) {
-  return 4u * (((n + kBlock - 1) / kBlock + kCopies - 1) / kCopies);
+  const uint64_t runs = ((n + kBlock - 1) / kBlock + kListRun - 1) / kListRun;
+  return 4u * kListRun * ((runs + kCopies - 1) / kCopies);
 }
 
 // Queue items of a batch of n messages: at most ceil(n / 64) whole ones and
@@ -1528,9 +1553,9 @@ int resident_grid(const void* kernel, const kb_tile* tile, int cus, uint32_t* gr
 template <int V>
 const void* second_pass_kernel(const kb_tile* tile) {
   if constexpr (V <= kMixed) {
-    if (tile && tile->staging == KB_STAGING_DIRECT) return reinterpret_cast<const void*>(&k_second<V, false>);
+    if (tile && tile->staging == KB_STAGING_DIRECT) return reinterpret_cast<const void*>(&k_second<V, false, 2>);
   }
-  return reinterpret_cast<const void*>(&k_second<V, true>);
+  return reinterpret_cast<const void*>(&k_second<V, true, 2>);
 }
 
 // The persistent form (two passes) or, with mode KB_MODE_PER_BUCKET, the
@@ -1566,14 +1591,17 @@ int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hi
   a.order = w.order;
   a.items = w.items;
   a.steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 4u;
-  // at most eight split messages per SIMD: one 8-group split item for each
-  // SIMD's front wave (SHA-3 variants; the per-bucket form takes none)
-  a.split_cap = V <= kMixed && !per_bucket ? 8u * 4u * static_cast<uint32_t>(cus) : 0u;
+  // at most two split messages per SIMD: one wide split item (a state per
+  // half-wave) for each SIMD's front wave (SHA-3 variants; the per-bucket
+  // form takes none)
+  a.split_cap = V <= kMixed && !per_bucket ? kWideStates * 4u * static_cast<uint32_t>(cus) : 0u;
   a.class_steps = 0;
   a.class_threads = 0;
   for (int c = 0; tile && c < KB_NB_CLASSES; ++c) {  // ranges checked by check_tile
     a.class_steps |= static_cast<uint64_t>(tile->class_steps[c] & 0xFF) << (8 * c);
-    a.class_threads |= static_cast<uint32_t>(tile->class_threads[c] & 0xF) << (4 * c);
+    const int32_t tc = tile->class_threads[c];
+    const uint32_t ct = tc == KB_THREADS_WIDE ? 2u : static_cast<uint32_t>(tc);
+    a.class_threads |= ct << (4 * c);
   }
   a.lanes = static_cast<uint64_t>(grid2) * kBlock;
   a.hash = per_bucket ? 0 : 1;
@@ -1584,6 +1612,11 @@ int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hi
   }
   KB_HIP(hipGetLastError());
   {
+    TimedLaunch tl(s, KB_KERNEL_SCHEDULE);
+    hipLaunchKernelGGL((k_second<V, kb::kPrefetch<V>, 1>), dim3(grid2), dim3(kBlock), 0, s, a);
+  }
+  KB_HIP(hipGetLastError());
+  if (!per_bucket) {
     TimedLaunch tl(s, KB_KERNEL_SECOND_PASS);
     void* args[] = {&a};
     KB_HIP(hipLaunchKernel(second, dim3(grid2), dim3(kBlock), args, 0, s));
@@ -1663,8 +1696,8 @@ int check_tile(const kb_tile* t) {
   for (int c = 0; c < KB_NB_CLASSES; ++c) {
     if (t->class_steps[c] < 0 || t->class_steps[c] > 255)
       return fail(KB_EINVAL, "tile.class_steps[%d] must be in 0..255", c);
-    if (t->class_threads[c] != 0 && t->class_threads[c] != 1 && t->class_threads[c] != 5)
-      return fail(KB_EINVAL, "tile.class_threads[%d] must be 0, 1 or 5", c);
+    if (t->class_threads[c] != 0 && t->class_threads[c] != 1 && t->class_threads[c] != KB_THREADS_WIDE)
+      return fail(KB_EINVAL, "tile.class_threads[%d] must be 0, 1 or %d", c, KB_THREADS_WIDE);
   }
   return KB_OK;
 }
@@ -1746,7 +1779,11 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
       const uint64_t blocks = (lv.m[first] + kBlock - 1) / kBlock;
       {
         TimedLaunch tl(s, KB_KERNEL_TREE);
-        if (w8 || first > 0)
+        if (first > 0)
+          hipLaunchKernelGGL((k_tree<V, kBlock, kb::kPrefetch<V>, true, kBlock, true>),
+                             dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data, total,
+                             leaf, w->tree, root, first, levels, L, lv);
+        else if (w8)
           hipLaunchKernelGGL((k_tree<V, kBlock, kb::kPrefetch<V>, true>),
                              dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, s, data, total,
                              leaf, w->tree, root, first, levels, L, lv);
@@ -1760,7 +1797,7 @@ int merkle_impl(const uint8_t* data, uint64_t total, uint64_t leaf, uint8_t* roo
     } else {
       {
         TimedLaunch tl(s, KB_KERNEL_TREE);
-        hipLaunchKernelGGL((k_tree<V, kTreeTopThreads, false, true, kTreeTop>), dim3(1),
+        hipLaunchKernelGGL((k_tree<V, kTreeTopThreads, false, true, kTreeTop, true>), dim3(1),
                            dim3(kTreeTopThreads), 0, s, data, total, leaf, w->tree, root, first,
                            L - first, L, lv);
       }
@@ -2137,7 +2174,7 @@ int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_dat
       if (c < KB_NB_CLASSES && !((present >> c) & 1u)) continue;
       kb_tile t = base;
       for (int k = 0; k < KB_NB_CLASSES; ++k)
-        if ((present >> k) & 1u) t.class_threads[k] = k >= c ? 5 : 1;
+        if ((present >> k) & 1u) t.class_threads[k] = k >= c ? KB_THREADS_WIDE : 1;
       rc = consider(t);
     }
   }
@@ -2334,7 +2371,7 @@ int keccak_timing_read(double* total_ms, uint64_t* launches) {
 }
 
 int keccak_timing_read_kernel(int kind, double* total_ms, uint64_t* launches) {
-  if (kind < KB_KERNEL_FIRST_PASS || kind > KB_KERNEL_WIDE) {
+  if (kind < KB_KERNEL_FIRST_PASS || kind > KB_KERNEL_SCHEDULE) {
     g_err.clear();
     return fail(KB_EINVAL, "unknown kernel kind %d", kind);
   }

@@ -49,6 +49,7 @@ class KbError(RuntimeError):
 
 NB_CLASSES = 8
 STAGING_DEFAULT, STAGING_DIRECT, STAGING_PREFETCH = 0, 1, 2
+THREADS_WIDE = 32  # class_threads value of the wide split tail (32 lanes per state)
 
 
 class Tile(ctypes.Structure):
@@ -641,7 +642,8 @@ def timing_enable(on: bool = True):
     _check(load_library().keccak_timing_enable(1 if on else 0))
 
 
-KERNELS = {"first_pass": 0, "second_pass": 1, "plain": 2, "split": 3, "tree": 4, "wide": 5}
+KERNELS = {"first_pass": 0, "second_pass": 1, "plain": 2, "split": 3, "tree": 4, "wide": 5,
+           "schedule": 6}
 
 
 def timing_read(kernel: str | None = None) -> tuple[float, int]:

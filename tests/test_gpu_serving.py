@@ -130,11 +130,11 @@ def test_cached_tile_is_chosen_and_matches_oracle(kb, o2, tmp_path, monkeypatch)
     assert rejected == 0
     assert kb.tune_lookup(-1, b.n, path=path).as_dict() == tuned.as_dict()
     # a distinctive tile for SHA3-512 over the same batch: direct staging, two
-    # waves per SIMD, every class of 16 or more blocks in the five-lane form
+    # waves per SIMD, every class of 16 or more blocks in the wide split tail
     t = kb.Tile()
     t.waves_per_simd, t.steps_per_item, t.staging = 2, 2, kb.STAGING_DIRECT
     for c in range(kb.NB_CLASSES):
-        t.class_threads[c] = 5 if c >= 4 else 1
+        t.class_threads[c] = kb.THREADS_WIDE if c >= 4 else 1
         t.class_steps[c] = 1 + c
     kb.tune_store(path, 3, b.n, t, 1.0)
     monkeypatch.setenv("KBATCH_TUNE", path)

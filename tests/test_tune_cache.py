@@ -28,7 +28,7 @@ def _tile(kb, **kw):
 
 def test_store_then_lookup_round_trip(kb, tmp_path):
     path = str(tmp_path / "tune.json")
-    t = _tile(kb, class_steps={0: 4, 4: 16}, class_threads={7: 5, 4: 1})
+    t = _tile(kb, class_steps={0: 4, 4: 16}, class_threads={7: 32, 4: 1})
     kb.tune_store(path, 1, 1 << 20, t, 1.25, arch="gfx950", rocm="7.2")
     doc = json.load(open(path))
     assert doc["format"] == "kbatch-tune-1"
