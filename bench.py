@@ -165,6 +165,36 @@ def bench_uneven(args, kbatch, workloads, torch, dev):
                       "steps": args.steps, "warmup": args.warmup, **res}), flush=True)
 
 
+def bench_small(args, kbatch, workloads, torch, dev):
+    """4096 messages of 64 B, SHA3-256: the plain one-thread-per-message
+    launch and the persistent form, each digest compared with the CPU
+    oracle, which is timed on the same batch."""
+    from oracle import o2
+    n = 4096
+    b = workloads.uniform(n, MSG_BYTES, seed=1, variant=VARIANT)
+    data = torch.from_numpy(b.data).to(dev)
+    offs = torch.from_numpy(b.offsets).to(dev)
+    lens = torch.from_numpy(b.lengths).to(dev)
+    t0 = time.perf_counter()
+    want = o2.sha3_batch(256, b.data, b.offsets, b.lengths, threads=1)
+    cpu_s = time.perf_counter() - t0
+    res = {}
+    for mode in ("plain", "persistent"):
+        out = torch.empty((n, 32), dtype=torch.uint8, device=dev)
+        fn = lambda: kbatch.keccak_batch(VARIANT, data, offs, lens, out=out, mode=mode,
+                                         check_bounds=False)
+        t = time_steps(torch, fn, args.steps, args.warmup)
+        res[mode] = {"us_per_batch": round(t * 1e6, 2), "mhash_s": round(n / t / 1e6, 2),
+                     "bit_exact": bool(np.array_equal(out.cpu().numpy(), want))}
+    print(json.dumps({"config": {"workload": "sha3_256_uniform_4096x64B", "seed": 1},
+                      "steps": args.steps, "warmup": args.warmup, **res,
+                      "cpu_oracle": {"us_per_batch": round(cpu_s * 1e6, 1),
+                                     "mhash_s": round(n / cpu_s / 1e6, 4), "threads": 1}}),
+          flush=True)
+    if not all(r["bit_exact"] for r in res.values()):
+        sys.exit(3)
+
+
 def bench_merkle(args, kbatch, workloads, torch, dev):
     """1 GiB of seeded bytes in 4 KiB leaves, SHA3-256, up to one root."""
     print("[bench] generating 1 GiB tree input (seed 5)", file=sys.stderr, flush=True)
@@ -330,8 +360,9 @@ def main():
     ap.add_argument("--serve-eager", action="store_true",
                     help="serving: steps as separate copies and launches instead of one graph replay")
     ap.add_argument("--workload", default="uniform",
-                    choices=("uniform", "uneven", "merkle", "serving", "latency"),
-                    help="uniform: 2^24 x 64 B SHA3-256 (the reported metric); uneven: 2^20 "
+                    choices=("uniform", "small", "uneven", "merkle", "serving", "latency"),
+                    help="uniform: 2^24 x 64 B SHA3-256 (the reported metric); small: 4096 x "
+                         "64 B, plain launch against the CPU oracle; uneven: 2^20 "
                          "mixed-variant messages, log-uniform lengths in [0, 16 KiB]; merkle: "
                          "1 GiB in 4 KiB leaves; serving: Poisson request stream; latency: "
                          "1 to 32768 long messages, one thread vs five or 32 lanes per message")
@@ -359,6 +390,8 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 3,
                           "gbps_read_plus_write": [round(g, 1) for g in gbps]}), flush=True)
         return
+    if args.workload == "small":
+        return bench_small(args, kbatch, workloads, torch, dev)
     if args.workload == "uneven":
         return bench_uneven(args, kbatch, workloads, torch, dev)
     if args.workload == "merkle":

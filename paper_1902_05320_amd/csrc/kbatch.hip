@@ -751,11 +751,18 @@ constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
 
 // The first CTL_SPLIT_N positions of the bucketed order (the longest
 // messages) go to the split form: the messages of at least
-// max(kSplitMinKey, 4 x the mean, 2 x the blocks per resident lane) blocks,
-// at most `split_cap` of them.  Below the last bound the batch's throughput,
-// not its longest chain, sets the time, and a split item (eight messages per
-// wave) costs throughput.
+// max(kSplitMinKey, 2 x the blocks per resident lane) blocks, at most
+// `split_cap` of them.  Below the second bound the batch's throughput, not
+// its longest chain, sets the time, and a split item (two messages per wave)
+// costs throughput.  (An earlier bound of 4 x the mean block count kept a
+// batch of a few equal long messages out of the split form: 8 x 64 KiB ran
+// at 11.0 us per block of the chain, now 3.8.)
 constexpr uint32_t kSplitMinKey = 32;
+// Wide split items per SIMD's front wave.  Two measured against one
+// (interleaved A/B): serving stream p50 5.23-5.25 against 5.17 ms, p99
+// 7.87-7.95 against 7.70-7.78 ms; 4096 x 16 KiB 8.6 against 14.2 us per
+// block of the chain; the uneven batch level.  One keeps the serving tail.
+constexpr uint32_t kSplitItemsPerSimd = 1;
 
 // The plan, made by one workgroup of the second pass once the first pass
 // has finished.  Folds the partial histograms, writes the bucket
@@ -853,7 +860,7 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
   const uint64_t avg = useful / (ndef ? ndef : 1u);
   // bucket starts; the split range ends where the keys drop below kmin
   const uint64_t per_lane = 2u * useful / (a.lanes ? a.lanes : 1u);
-  uint64_t kmin64 = 4u * avg > kSplitMinKey ? 4u * avg : kSplitMinKey;
+  uint64_t kmin64 = kSplitMinKey;
   if (per_lane > kmin64) kmin64 = per_lane;
   const uint32_t kmin = kmin64 < kKeyBins - 1u ? static_cast<uint32_t>(kmin64) : kKeyBins - 1u;
   if (t == 0) s_split = ndef;  // until a bucket that stays one lane per message
@@ -1189,17 +1196,16 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
     // positions [0, split_n)) two at a time, one per half-wave, in the wide
     // lane-split form (one state word per lane), whose chain of permutations
     // runs about three times as fast as one thread's.  The exchange areas are
-    // this wave's own staging rows.  (SHA-3 variants; the XOFs keep one lane
-    // per message.)
-    const uint32_t split_n = V <= kMixed ? ctl[CTL_SPLIT_N] : 0u;
-    if constexpr (V <= kMixed) {
+    // this wave's own staging rows.  The XOFs squeeze in the same form.
+    const uint32_t split_n = ctl[CTL_SPLIT_N];
+    {
       if (front && split_n) {
         namespace wd = kb::wide;
         uint64_t* area = reinterpret_cast<uint64_t*>(lds + (threadIdx.x & ~63u) * S::kRowDw);
         const uint32_t half = lane / wd::kHalfLanes;
         wd::WideLane L;
         wd::setup(L, lane % wd::kHalfLanes, area + half * wd::kAreaSlots);
-        const int slot_dw = static_cast<int>(out_stride_of<V>() / 4u);
+        const int slot_dw = V >= kShake128 ? 0 : static_cast<int>(out_stride_of<V <= kMixed ? V : 1>() / 4u);
         uint32_t* split_ctr = reinterpret_cast<uint32_t*>(queues + kQueues * (kLine / 2));
         __builtin_amdgcn_s_setprio(3);
         for (;;) {
@@ -1213,7 +1219,11 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
             const uint32_t i = a.order[pos];
             const int var = V == kMixed ? a.vars[i] : V;
             uint32_t* o = reinterpret_cast<uint32_t*>(a.out + static_cast<uint64_t>(i) * a.stride);
-            if (V == kMixed && var > 3) {
+            if constexpr (V >= kShake128) {
+              Lane w;
+              wide_absorb<V>(w, a.data + a.offs[i], a.lens[i], V, L);
+              wide_xof<V>(w, a.out + static_cast<uint64_t>(i) * a.stride, a.stride, L);
+            } else if (V == kMixed && var > 3) {
               wd::store_word(o, Lane{0u, 0u}, 0, slot_dw, L);
             } else {
               Lane w;
@@ -1591,10 +1601,9 @@ int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hi
   a.order = w.order;
   a.items = w.items;
   a.steps = tile && tile->steps_per_item > 0 ? static_cast<uint32_t>(tile->steps_per_item) : 4u;
-  // at most two split messages per SIMD: one wide split item (a state per
-  // half-wave) for each SIMD's front wave (SHA-3 variants; the per-bucket
-  // form takes none)
-  a.split_cap = V <= kMixed && !per_bucket ? kWideStates * 4u * static_cast<uint32_t>(cus) : 0u;
+  // at most kSplitItemsPerSimd wide split items (a state per half-wave) for
+  // each SIMD's front wave (the per-bucket form takes none)
+  a.split_cap = !per_bucket ? kSplitItemsPerSimd * kWideStates * 4u * static_cast<uint32_t>(cus) : 0u;
   a.class_steps = 0;
   a.class_threads = 0;
   for (int c = 0; tile && c < KB_NB_CLASSES; ++c) {  // ranges checked by check_tile
