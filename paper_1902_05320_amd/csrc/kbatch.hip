@@ -1,22 +1,24 @@
 // libkbatch: batch SHA-3 on gfx950 -- kernels, scheduler and the C ABI.
 //
-// keccak_batch (persistent form) is three launches on the caller's stream,
+// keccak_batch (persistent form) is four launches on the caller's stream,
 // with no host synchronisation:
 //   k_first   one 64-message chunk of arrival order per wave: a chunk of
 //             one-block messages is hashed on the spot; any other chunk is
 //             deferred (its block-count keys nb = floor(L/R) + 1 counted,
 //             bins 1..4094 exact and 4095 = "4095 or more", its index
 //             listed).
-//   k_second<.., 1> (schedule)  one workgroup makes the plan (bucket starts
-//             in descending nb, longest first; queue items of about
-//             `steps_per_item` permutations per lane; the range of the
-//             longest messages that the wide split form hashes), the grid
-//             fills the queue and scatters the deferred messages into
-//             bucketed order.
+//   k_second<.., 0> (plan)  one workgroup: bucket starts in descending nb,
+//             longest first; queue items of about `steps_per_item`
+//             permutations per lane; the range of the longest messages that
+//             the wide split form hashes.
+//   k_second<.., 1> (tiles)  the grid fills the queue and scatters the
+//             deferred messages into bucketed order.
 //   k_second<.., 2> (hashing)  a resident grid: each SIMD's front wave takes
 //             the split range and then the longest items at raised
 //             priority, the other waves the shortest ones.
-// On a batch with nothing deferred the last two find no work and return.
+// Kernel boundaries order each launch's writes before the next one's reads,
+// so no workgroup waits on another or fences.  On a batch with nothing
+// deferred the last three find no work and return.
 // The plain form is one k_plain launch in arrival order; the per-bucket form
 // runs both passes without hashing, reads the bucket sizes back, and
 // launches k_plain once per non-empty bucket.
@@ -68,18 +70,14 @@ enum : int {
   CTL_MAXKEY = 4,       // largest block-count key deferred
   CTL_PRIO_KEY = 5,     // front waves raise their priority on items of at least this many blocks
   CTL_SPLIT_N = 6,      // bucketed order positions [0, CTL_SPLIT_N) are hashed in the split form
-  CTL_SPIN_LIMIT = 7,   // set if a second-pass workgroup gave up waiting for the tiles
   CTL_USEFUL = 8,       // uint64 (words 8, 9): block counts of the deferred messages
   CTL_DPREFIX = 16,     // words 16..24: exclusive prefix of the deferred sub-list lengths
   CTL_WORDS = 64
 };
 
-// Counters of the two passes, one 256-byte line each.
+// Counters of the second pass, one 256-byte line each.
 enum : uint32_t {
-  SY_EPOCH = 0,       // calls so far (the first pass's workgroup 0 counts this one)
-  SY_CLAIM = 1,       // second-pass tiles claimed
-  SY_DONE = 2,        // second-pass tiles finished
-  SY_PLAN_READY = 3,  // the epoch whose plan is complete
+  SY_CLAIM = 1,       // tiles claimed (line 0 is spare)
   kSyncCounters = 4
 };
 
@@ -797,8 +795,6 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
   if (t == 0) {
     ctl[CTL_DPREFIX + kCopies] = ndef_chunks;
     sync[SY_CLAIM * kLine] = 0u;
-    sync[SY_DONE * kLine] = 0u;
-    ctl[CTL_SPIN_LIMIT] = 0u;
     ctl[CTL_NDEF_CHUNKS] = ndef_chunks;
   }
   if (ndef_chunks == 0) {  // every chunk was hashed by the first pass
@@ -973,8 +969,6 @@ __global__ __launch_bounds__(kBlock, kFirstWaves<V>) void k_first(PassArgs a) {
   // the staging rows only: 40 KiB for the 136- and 144-byte rates, so four
   // workgroups fit on a CU
   __shared__ __align__(16) uint32_t lds[kBlock * S::kRowDw];
-  uint32_t* const sync = a.meta + M_SYNC;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sync[SY_EPOCH * kLine] += 1u;  // read by the second pass
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t nch = (a.n + 63u) / 64u;
   // (the wave index through readfirstlane: the compiler then sees the chunk
@@ -1092,17 +1086,13 @@ __device__ __forceinline__ void scatter_tile(const PassArgs& a, uint32_t tile, u
   __syncthreads();  // the LDS arrays are reused by the next tile
 }
 
-// A second-pass workgroup waits at most this many sleeps for the tiles of
-// the others (about a second); the tiles need microseconds, so the bound is
-// only a guard against a wait that could never end.
-constexpr uint32_t kSpinLimit = 1u << 22;
-
-// Second pass (see above), as two launches of one template: PH = 1 plans
-// and fills the queue and the bucketed order, PH = 2 hashes.  The kernel
-// boundary between them orders the scatter's writes before the hashing
-// reads, with no fence or wait in the hashing launch (measured against one
-// launch doing both: the uniform 2^24 x 64 B batch 1.632 against 1.643 ms,
-// the uneven 2^20 batch 2.575 against 2.540 ms).
+// Second pass (see above), as three launches of one template: PH = 0 makes
+// the plan, PH = 1 fills the queue and the bucketed order, PH = 2 hashes.
+// Kernel boundaries order the plan before the tiles and the tiles before
+// the hashing.  (Earlier forms did the plan and the tiles in the hashing
+// launch's workgroups, the others spinning on a published word and then
+// fencing: on the uneven 2^20 batch the plan and tiles took 84 us of it,
+// the acquire fences of hundreds of workgroups each invalidating an L2.)
 // On each SIMD one wave (the first to claim the SIMD's flag) takes items
 // from the front at raised issue priority while they are long, so the long
 // absorb chains that bound the makespan run back to back at full rate; the
@@ -1119,52 +1109,21 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
   constexpr uint32_t kStageDw = kBlock * S::kRowDw;
   constexpr uint32_t kLdsDw = kStageDw > 2 * kKeyBins ? kStageDw : 2 * kKeyBins;
   __shared__ __align__(16) uint32_t lds[kLdsDw];
-  __shared__ uint32_t s_tile, s_gave_up;
+  __shared__ uint32_t s_tile;
   static_assert(2 * kWideStates * kb::wide::kAreaSlots <= 64 * S::kRowDw,
                 "a wave's staging rows hold its wide exchange areas");
   const uint32_t* ctl = a.meta + M_CTL;
   uint32_t* const sync = a.meta + M_SYNC;
-  // The plan for this call (epoch E, counted by the first pass) is made by
-  // workgroup 0, which the dispatcher starts first, so it is always running;
-  // the others wait until it publishes E (electing the planner with an
-  // atomic on one word cost tens of microseconds: hundreds of workgroups
-  // contending for it).  The published word also says whether there is any
-  // work: when there is none (the first pass hashed every chunk), the waiting
-  // workgroups leave without an acquire fence, which on this chip
-  // invalidates the L2 and, in hundreds of workgroups at once, took about
-  // 0.1 ms.  The wait is bounded (kSpinLimit sleeps, with relaxed loads); a
-  // workgroup that gives up flags it and leaves.
-  if constexpr (PH == 1) {
-    const uint32_t epoch = __builtin_amdgcn_readfirstlane(load_relaxed(&sync[SY_EPOCH * kLine])) & 0x7FFFFFFFu;
-    uint32_t* const ready = &sync[SY_PLAN_READY * kLine];  // (epoch << 1) | any work
-    if (blockIdx.x == 0) {
-      make_plan(a, lds);
-      __syncthreads();  // every thread's plan writes are done
-      if (threadIdx.x == 0)
-        __hip_atomic_store(ready, (epoch << 1) | (ctl[CTL_TILES] ? 1u : 0u), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      if (!__builtin_amdgcn_readfirstlane(ctl[CTL_TILES])) return;  // the first pass hashed everything
-    } else {
-      if (threadIdx.x == 0) {
-        uint32_t spins = 0, r = load_relaxed(ready);
-        while ((r >> 1) != epoch && spins < kSpinLimit) {
-          __builtin_amdgcn_s_sleep(8);
-          ++spins;
-          r = load_relaxed(ready);
-        }
-        s_gave_up = (r >> 1) != epoch ? 2u : (r & 1u);  // 2: gave up, 0: nothing to do, 1: work
-        if (s_gave_up == 2u) a.meta[M_CTL + CTL_SPIN_LIMIT] = 1u;
-      }
-      __syncthreads();
-      if (__builtin_amdgcn_readfirstlane(s_gave_up) != 1u) return;
-      __threadfence();  // acquire: the plan is visible from here on
-    }
-    const uint32_t tiles = __builtin_amdgcn_readfirstlane(load_relaxed(&ctl[CTL_TILES]));
-    const uint32_t item_tiles = load_relaxed(&ctl[CTL_ITEM_TILES]);
+  if constexpr (PH == 0) {
+    make_plan(a, lds);  // one workgroup
+    return;
+  } else if constexpr (PH == 1) {
     // Tiles are claimed one at a time from a counter.  One thread claims;
     // the loop condition is a scalar read after a barrier, so the loop (with
-    // the barriers in it) is uniform as the compiler sees it.  The hashing
-    // launch that follows sees every tile's writes (kernel boundary).
+    // the barriers in it) is uniform as the compiler sees it.
+    const uint32_t tiles = __builtin_amdgcn_readfirstlane(ctl[CTL_TILES]);
+    if (!tiles) return;  // the first pass hashed everything
+    const uint32_t item_tiles = ctl[CTL_ITEM_TILES];
     if (threadIdx.x == 0) s_tile = atomicAdd(&sync[SY_CLAIM * kLine], 1u);
     __syncthreads();
     uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
@@ -1618,6 +1577,11 @@ int run_two_pass(const Batch& b, Workspace& w, int mode, const kb_tile* tile, hi
   {
     TimedLaunch tl(s, KB_KERNEL_FIRST_PASS);
     hipLaunchKernelGGL(k_first<V>, dim3(grid1), dim3(kBlock), 0, s, a);
+  }
+  KB_HIP(hipGetLastError());
+  {
+    TimedLaunch tl(s, KB_KERNEL_SCHEDULE);
+    hipLaunchKernelGGL((k_second<V, kb::kPrefetch<V>, 0>), dim3(1), dim3(kBlock), 0, s, a);
   }
   KB_HIP(hipGetLastError());
   {
