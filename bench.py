@@ -274,15 +274,32 @@ def bench_serving(args, kbatch, workloads, torch, dev):
     4 GiB device-resident pool; continuous batching through the library's
     server.  Reports p50/p99 latency (submit to digests on the host) and the
     hashed throughput, and checks a sample of requests against the same
-    request hashed alone."""
+    request hashed alone.
+
+    With --serve-h2d each request's messages instead arrive packed back to
+    back in pinned host memory (a slice of a 4 GiB pinned copy of the pool):
+    at arrival the request is copied into a ring region of the device pool
+    and then submitted, and its latency runs from its arrival, so it
+    includes the wait for the copy link and the host-to-device copy."""
+    from collections import deque
     duration, warm = args.serve_seconds, 2.0
+    h2d = args.serve_h2d
     print("[bench] generating 4 GiB pool and request stream (seed 4)", file=sys.stderr, flush=True)
     pool_np, reqs = workloads.serving_stream(duration + warm, 2000.0, 4 << 30, seed=4)
     pool = torch.from_numpy(pool_np).to(dev)
+    host_pool = copy_stream = None
+    if h2d:
+        host_pool = torch.from_numpy(pool_np).pin_memory()
+        copy_stream = torch.cuda.Stream(device=dev)
     srv = kbatch.Server(pool, max_step_msgs=args.serve_step_msgs, steps_in_flight=args.serve_in_flight,
                         graphs=not args.serve_eager)
     lat, nbytes, results, sample = [], 0, {}, set(range(0, len(reqs), max(1, len(reqs) // 200)))
     inflight = {}
+    extra_ms = {}      # H2D: arrival to submit (waiting for the link, the copy) per request
+    src_of = {}        # H2D: where a sampled request's bytes sit in the host pool
+    ring = deque()     # H2D: (start, end, request index) of device regions still in use
+    ring_pos = 0
+    pool_n = pool.numel()
     t0 = time.perf_counter()
 
     def drain(wait_ms=0):
@@ -292,10 +309,13 @@ def bench_serving(args, kbatch, workloads, torch, dev):
             r = reqs[idx]
             digests, ms = srv.result(rid, r.offsets.size)
             if r.arrival_s >= warm:
-                lat.append(ms)
+                lat.append(ms + extra_ms.pop(idx, 0.0))
                 nbytes += int(r.lengths.sum())
             if idx in sample:
                 results[idx] = digests
+
+    def region_free(lo, hi):
+        return all(e <= lo or b >= hi or i not in inflight.values() for b, e, i in ring)
 
     for idx, r in enumerate(reqs):
         while True:
@@ -305,7 +325,30 @@ def bench_serving(args, kbatch, workloads, torch, dev):
             drain()
             if r.arrival_s - (time.perf_counter() - t0) > 0.0005:
                 time.sleep(0.0002)
-        inflight[srv.submit(r.variant, r.offsets, r.lengths)] = idx
+        if h2d:
+            lens = r.lengths.astype(np.int64)
+            total = int(lens.sum())
+            rel = np.zeros(lens.size, dtype=np.int64)
+            np.cumsum(lens[:-1], out=rel[1:])
+            src = int(r.offsets[0]) % max(1, pool_n - total)
+            if ring_pos + total > pool_n:
+                ring_pos = 0
+            while not region_free(ring_pos, ring_pos + total):
+                drain(wait_ms=1)
+            while ring and ring[0][2] not in inflight.values():
+                ring.popleft()
+            with torch.cuda.stream(copy_stream):
+                pool[ring_pos:ring_pos + total].copy_(host_pool[src:src + total], non_blocking=True)
+            copy_stream.synchronize()
+            ring.append((ring_pos, ring_pos + total, idx))
+            rid = srv.submit(r.variant, rel + ring_pos, lens)
+            extra_ms[idx] = 1e3 * ((time.perf_counter() - t0) - r.arrival_s)
+            if idx in sample:
+                src_of[idx] = (src, rel)
+            ring_pos = (ring_pos + total + 255) // 256 * 256
+        else:
+            rid = srv.submit(r.variant, r.offsets, r.lengths)
+        inflight[rid] = idx
         if idx % 256 == 0:
             print(f"[bench] serving: submitted {idx}/{len(reqs)}", file=sys.stderr, flush=True)
     while inflight:
@@ -316,10 +359,16 @@ def bench_serving(args, kbatch, workloads, torch, dev):
     ok = 0
     for idx, digests in results.items():
         r = reqs[idx]
-        o = torch.from_numpy(r.offsets.astype(np.int64)).to(dev)
-        ln = torch.from_numpy(r.lengths.astype(np.int64)).to(dev)
         v = torch.full((r.offsets.size,), r.variant, dtype=torch.uint8, device=dev)
-        alone = kbatch.keccak_batch_mixed(v, pool, o, ln).cpu().numpy()
+        if h2d:
+            src, rel = src_of[idx]
+            data = host_pool[src:src + int(r.lengths.sum())].to(dev)
+            o = torch.from_numpy(rel).to(dev)
+        else:
+            data = pool
+            o = torch.from_numpy(r.offsets.astype(np.int64)).to(dev)
+        ln = torch.from_numpy(r.lengths.astype(np.int64)).to(dev)
+        alone = kbatch.keccak_batch_mixed(v, data, o, ln).cpu().numpy()
         ok += int(np.array_equal(alone, digests))
     lat = np.array(lat)
     measured_s = max(wall - warm, 1e-9)
@@ -327,7 +376,8 @@ def bench_serving(args, kbatch, workloads, torch, dev):
                                  "seed": 4, "pool_bytes": 4 << 30, "seconds": duration,
                                  "warmup_s": warm, "max_step_msgs": args.serve_step_msgs,
                                  "steps_in_flight": args.serve_in_flight,
-                                 "step_form": "eager" if args.serve_eager else "graph"},
+                                 "step_form": "eager" if args.serve_eager else "graph",
+                                 "inputs": "pinned host, copied at arrival" if h2d else "device pool"},
                       "requests": len(lat), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
                       "mean_ms": round(float(lat.mean()), 3),
@@ -357,6 +407,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-in-flight", type=int, default=2, help="serving: steps in flight")
     ap.add_argument("--serve-step-msgs", type=int, default=1 << 16, help="serving: messages per step")
+    ap.add_argument("--serve-h2d", action="store_true",
+                    help="serving: requests arrive in pinned host memory and are copied to the "
+                         "device at arrival (latency includes the copy)")
     ap.add_argument("--serve-eager", action="store_true",
                     help="serving: steps as separate copies and launches instead of one graph replay")
     ap.add_argument("--workload", default="uniform",

@@ -160,10 +160,10 @@ int keccak_batch_xof(int security, const uint8_t* d_data, const uint64_t* d_offs
 
 /*
  * keccak_batch_xof_ex -- keccak_batch_xof with an explicit scheduling mode
- * (KB_MODE_PERSISTENT, _PLAIN, _PER_BUCKET or _SPLIT; in the split form five
- * lanes share each state and squeeze it, which shortens each message's chain
- * of permutations for a few long messages).  Same output; KB_EINVAL for an
- * unknown mode.
+ * (KB_MODE_PERSISTENT, _PLAIN, _PER_BUCKET, _SPLIT or _WIDE; in the split
+ * forms five or 32 lanes share each state and squeeze it, which shortens each
+ * message's chain of permutations for a few long messages).  Same output;
+ * KB_EINVAL for an unknown mode.
  */
 int keccak_batch_xof_ex(int security, const uint8_t* d_data, const uint64_t* d_offsets,
                         const uint64_t* d_lengths, uint64_t n, uint64_t out_len, uint8_t* d_out,
