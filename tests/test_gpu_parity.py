@@ -257,9 +257,10 @@ def test_merkle_top_workgroup_boundaries(kb, o2, v):
 
 @pytest.mark.parametrize("v", [1, 3])
 def test_merkle_deep_trees(kb, o2, v):
-    # more than 2^18 leaves: more than 1024 nodes remain after the leaf
-    # launch's 8 levels, so a middle launch runs before the last workgroup;
-    # odd counts at most levels carry unpaired nodes up
+    # more than 2^11 leaves: more than 1024 nodes remain after the leaf
+    # launch's one level, so middle launches (up to 8 levels each, the
+    # narrowest in the five-lane and wide forms) run before the last
+    # workgroup; odd counts at most levels carry unpaired nodes up
     import torch
     rng = np.random.Generator(np.random.PCG64(60 + v))
     for n_leaves, leaf in ((300_001, 1), (2**19 + 3, 5)):
