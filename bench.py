@@ -405,7 +405,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the library's copy probe over MIB MiB (for counter scaling)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-in-flight", type=int, default=2, help="serving: steps in flight")
+    ap.add_argument("--serve-in-flight", type=int, default=3, help="serving: steps in flight")
     ap.add_argument("--serve-step-msgs", type=int, default=1 << 16, help="serving: messages per step")
     ap.add_argument("--serve-h2d", action="store_true",
                     help="serving: requests arrive in pinned host memory and are copied to the "

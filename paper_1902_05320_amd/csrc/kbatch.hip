@@ -936,6 +936,8 @@ constexpr int kFirstWaves = V == kShake128 ? 2 : 3;
 // for byte the same (measured twice, with the blocks in either order).
 // (Arguments by value: a reference to the argument block would move it to
 // scratch.)
+constexpr uint32_t kDeferDirectKey = 16;
+
 template <int V>
 __device__ __attribute__((noinline)) void defer_chunk(uint32_t* meta, uint32_t* deferred, uint32_t seg,
                                                     uint32_t len, int var, uint64_t c, bool valid,
@@ -945,11 +947,16 @@ __device__ __attribute__((noinline)) void defer_chunk(uint32_t* meta, uint32_t* 
   const uint32_t x = (blockIdx.x / kListRun) % kCopies;
   uint32_t* const hist = meta + M_HIST + x * kKeyBins;
   const uint32_t key = valid ? key_of(blocks_of<V>(len, var)) : 0u;
-  uint64_t todo = __builtin_amdgcn_ballot_w64(valid);
+  // keys above kDeferDirectKey are rare and mostly distinct within a chunk:
+  // one atomic per lane, all issued at once; the frequent small keys are
+  // merged across the wave first, one atomic per distinct key
+  const bool direct = valid && key > kDeferDirectKey;
+  if (direct) atomicAdd(&hist[hist_slot(key)], 1u);
+  uint64_t todo = __builtin_amdgcn_ballot_w64(valid && !direct);
   while (todo) {  // wave-uniform: one pass per distinct key
     const uint32_t leader = static_cast<uint32_t>(__builtin_ctzll(todo));
     const uint32_t k = __builtin_amdgcn_readlane(key, leader);
-    const uint64_t same = __builtin_amdgcn_ballot_w64(valid && key == k) & todo;
+    const uint64_t same = __builtin_amdgcn_ballot_w64(valid && !direct && key == k) & todo;
     if (lane == leader) atomicAdd(&hist[hist_slot(k)], static_cast<uint32_t>(__builtin_popcountll(same)));
     todo &= ~same;
   }
