@@ -51,12 +51,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_first_sha3_256_2p24x64.
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1902_05320_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()[:16]
+    """The kernel sources' hash that the loaded library was built from (it
+    reports it in its version string), else the hash of the sources here."""
+    try:
+        from paper_1902_05320_amd import kbatch
+        v = kbatch.version()
+        if " src " in v and not v.endswith("unknown"):
+            return v.rsplit(" src ", 1)[1]
+    except Exception:
+        pass
+    from paper_1902_05320_amd import build
+    return build.source_hash()
 
 
 def load_traffic(src_hash: str):

@@ -54,9 +54,11 @@ enum kb_status {
 
 /* Scheduling forms of a batch (all give identical digests). */
 enum kb_mode {
-  KB_MODE_PERSISTENT = 0, /* two resident-grid launches: arrival order, hashing every
-                             64-message chunk of one-block messages at once; the other
-                             messages bucketed by block count and hashed longest first */
+  KB_MODE_PERSISTENT = 0, /* four launches, no host wait: arrival order, hashing every
+                             64-message chunk of one-block messages at once; then a plan,
+                             a scatter into buckets of equal block count, and a resident
+                             grid hashing the buckets longest first (the longest messages
+                             in the wide split form) */
   KB_MODE_PLAIN = 1,      /* one thread per message in arrival order, one launch (the
                              paper's "one thread per message", Section 4.1) */
   KB_MODE_PER_BUCKET = 2, /* bucket by block count, one plain launch per bucket (waits on
@@ -197,7 +199,7 @@ int merkle_root(int variant, const uint8_t* d_data, uint64_t total_len, uint64_t
  * Searches, keeping the fastest so far at each stage: resident waves per
  * SIMD {occupancy maximum, 1, 2, 3} x staging {prefetch, direct}; then
  * steps_per_item {1, 2, 4, 8, 16, 32}; then threads per state by
- * block-count class (the five-lane form from each class present upward, or
+ * block-count class (the wide split tail from each class present upward, or
  * one lane everywhere); then steps per queue item for each class present
  * {1, 4, 16}.  Every candidate's digests are first compared with the plain
  * form's bit for bit (a candidate that differs is discarded and counted in
@@ -428,7 +430,9 @@ int keccak_probe_copy(const uint8_t* d_src, uint8_t* d_dst, uint64_t bytes, doub
 /* Text of the last error on the calling host thread ("" if none). */
 const char* keccak_last_error(void);
 
-/* Library version string. */
+/* Library version string: "kbatch <version> (gfx950) src <hash>", where <hash>
+ * names the kernel sources the library was built from (the first 16 hex
+ * digits of the SHA-256 over the kernel source directory). */
 const char* keccak_version(void);
 
 #ifdef __cplusplus

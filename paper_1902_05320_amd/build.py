@@ -7,6 +7,7 @@ flag only guards against those instructions being formed).
 
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -34,12 +35,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (set HIPCC or install ROCm)")
 
 
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over the kernel source directory
+    (file name, NUL, contents, in name order); built into the library, which
+    reports it through keccak_version, so a measurement names the sources of
+    the library that ran."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def compile_flags() -> list[str]:
     return [
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function",
-        f"-I{INCLUDE}", f"-I{CSRC}",
+        f"-I{INCLUDE}", f"-I{CSRC}", f'-DKB_SOURCE_HASH="{source_hash()}"',
     ]
 
 

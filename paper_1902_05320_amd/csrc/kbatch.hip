@@ -69,7 +69,7 @@ enum : int {
   CTL_NDEF_CHUNKS = 3,  // chunks the first pass deferred
   CTL_MAXKEY = 4,       // largest block-count key deferred
   CTL_PRIO_KEY = 5,     // front waves raise their priority on items of at least this many blocks
-  CTL_SPLIT_N = 6,      // bucketed order positions [0, CTL_SPLIT_N) are hashed in the split form
+  CTL_SPLIT_N = 6,      // bucketed order positions [0, CTL_SPLIT_N) are hashed in the wide split form
   CTL_USEFUL = 8,       // uint64 (words 8, 9): block counts of the deferred messages
   CTL_DPREFIX = 16,     // words 16..24: exclusive prefix of the deferred sub-list lengths
   CTL_WORDS = 64
@@ -868,8 +868,8 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
     c_base += cnt[q];
   }
   __syncthreads();
-  // A bucket goes to the split form if its class's tile says five threads
-  // per state, or (no choice given) by the rule key >= kmin.  The split range
+  // A bucket goes to the split form if its class's tile says the wide split
+  // tail, or (no choice given) by the rule key >= kmin.  The split range
   // is the longest-first prefix of such buckets: it ends at the start of the
   // first non-empty bucket that stays one lane per message.
 #pragma unroll
@@ -1514,10 +1514,24 @@ int launch_wide(const Batch& b, const uint32_t* order, uint64_t first, uint64_t 
 // Workgroups of `kernel` that fit on the chip at once, capped by the tile's
 // waves per SIMD (a 256-thread workgroup is one wave on each of a CU's four
 // SIMDs).
+// The occupancy query is cached per (device, kernel): it does not change,
+// and asked on every call it was a large part of a small batch's host time.
+std::map<std::pair<int, const void*>, int> g_occupancy;
+
 int resident_grid(const void* kernel, const kb_tile* tile, int cus, uint32_t* grid) {
-  int per_cu = 0;
-  KB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
-  if (per_cu < 1) per_cu = 1;
+  int dev = 0, per_cu = 0;
+  KB_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_occupancy.find({dev, kernel});
+    if (it != g_occupancy.end()) per_cu = it->second;
+  }
+  if (per_cu == 0) {
+    KB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
+    if (per_cu < 1) per_cu = 1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_occupancy[{dev, kernel}] = per_cu;
+  }
   if (tile && tile->waves_per_simd > 0 && tile->waves_per_simd < per_cu) per_cu = tile->waves_per_simd;
   *grid = static_cast<uint32_t>(per_cu * cus);
   return KB_OK;
@@ -2145,7 +2159,7 @@ int keccak_autotune(int variant, const uint8_t* d_variants, const uint8_t* d_dat
     for (uint32_t key = 1; !rc && ndef_chunks && key < kKeyBins; ++key)
       if (fold[key]) present |= 1u << kb::nb_class_of(key);
   }
-  // 3. threads per state by class: the five-lane split form for the longest
+  // 3. threads per state by class: the wide split tail for the longest
   // classes (from class c up) and one lane per message below, for each c
   // present, and one lane everywhere
   if (!rc && present) {
@@ -2360,6 +2374,11 @@ int keccak_timing_read_kernel(int kind, double* total_ms, uint64_t* launches) {
 
 const char* keccak_last_error(void) { return g_err.c_str(); }
 
-const char* keccak_version(void) { return "kbatch 0.1 (gfx950)"; }
+// KB_SOURCE_HASH: the build's hash of the kernel sources (first 16 hex
+// digits of the SHA-256 over this directory's files, as the build computes it)
+#ifndef KB_SOURCE_HASH
+#define KB_SOURCE_HASH "unknown"
+#endif
+const char* keccak_version(void) { return "kbatch 0.1 (gfx950) src " KB_SOURCE_HASH; }
 
 }  // extern "C"
