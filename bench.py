@@ -188,8 +188,14 @@ def bench_small(args, kbatch, workloads, torch, dev):
         out = torch.empty((n, 32), dtype=torch.uint8, device=dev)
         fn = lambda: kbatch.keccak_batch(VARIANT, data, offs, lens, out=out, mode=mode,
                                          check_bounds=False)
-        t = time_steps(torch, fn, args.steps, args.warmup)
+        t = time_steps(torch, fn, args.steps, args.warmup, lambda: kbatch.timing_enable(True))
+        k_ms, k_n = kbatch.timing_read()
+        kbatch.timing_enable(False)
+        # wall time per call includes the Python binding's per-call work;
+        # the kernels' own time (HIP events around each launch) does not
         res[mode] = {"us_per_batch": round(t * 1e6, 2), "mhash_s": round(n / t / 1e6, 2),
+                     "kernel_us_per_batch": round(1e3 * k_ms / args.steps, 2),
+                     "launches_per_batch": k_n // args.steps,
                      "bit_exact": bool(np.array_equal(out.cpu().numpy(), want))}
     print(json.dumps({"config": {"workload": "sha3_256_uniform_4096x64B", "seed": 1},
                       "steps": args.steps, "warmup": args.warmup, **res,
