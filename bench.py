@@ -243,7 +243,7 @@ def bench_latency(args, kbatch, workloads, torch, dev):
         nb = size // 136 + 1
         row = {"messages": k, "bytes_each": size, "blocks_each": nb}
         ref = None
-        for mode in ("plain", "persistent", "split", "wide"):
+        for mode in ("plain", "persistent", "split", "wide", "pair"):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch(1, data, offs, lens, out=out, mode=mode,
                                              check_bounds=False)
@@ -264,7 +264,7 @@ def bench_latency(args, kbatch, workloads, torch, dev):
         nb = size // 136 + 1
         row = {"messages": k, "bytes_each": size, "blocks_each": nb, "out_len": 32}
         ref = None
-        for mode in ("plain", "persistent", "split", "wide"):
+        for mode in ("plain", "persistent", "split", "wide", "pair"):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch_xof(256, data, offs, lens, 32, out=out, mode=mode,
                                                  check_bounds=False)

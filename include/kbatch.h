@@ -67,10 +67,14 @@ enum kb_mode {
                              messages per wave in arrival order (the serial absorb chain
                              of Section 3.2 runs about twice as fast per message, at a
                              fraction of the batch throughput) */
-  KB_MODE_WIDE = 4        /* wide latency form: one 64-bit state word per lane, 32 lanes
+  KB_MODE_WIDE = 4,       /* wide latency form: one 64-bit state word per lane, 32 lanes
                              per state, two messages per wave in arrival order (each
                              lane issues about twenty VALU instructions per round, with
                              two exchanges through LDS; for the fewest, longest chains) */
+  KB_MODE_PAIR = 5        /* pair form: two lanes per state, each holding one 32-bit half
+                             of every state word, 32 messages per wave in arrival order
+                             (about 1.5 times one thread's chain speed at a third more
+                             issue slots per permutation) */
 };
 
 /*
@@ -395,7 +399,8 @@ enum kb_kernel {
   KB_KERNEL_SPLIT = 3,       /* lane-split form */
   KB_KERNEL_TREE = 4,        /* tree mode */
   KB_KERNEL_WIDE = 5,        /* wide lane-split form */
-  KB_KERNEL_SCHEDULE = 6     /* persistent form: the plan and the bucketing scatter */
+  KB_KERNEL_SCHEDULE = 6,    /* persistent form: the plan and the bucketing scatter */
+  KB_KERNEL_PAIR = 7         /* pair form */
 };
 
 /* keccak_timing_read restricted to the kernels of one kind; KB_EINVAL for

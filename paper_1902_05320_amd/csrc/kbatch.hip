@@ -44,6 +44,7 @@
 #include "kbatch.h"
 #include "sponge_device.h"
 #include "split_device.h"
+#include "pair_device.h"
 #include "wide_device.h"
 
 using kb::kMixed;
@@ -460,6 +461,97 @@ __global__ __launch_bounds__(kWideBlock) void k_wide(const uint8_t* __restrict__
     wide_absorb<V>(a, data + offs[i], lens[i], var, L);
     const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
     wd::store_word(o, a, dw, slot_dw, L);
+  }
+}
+
+// The pair form (two lanes per state, each holding one 32-bit half of every
+// state word): absorb one message, the next block's halves loaded before the
+// current block's permutation.
+template <int V>
+__device__ __forceinline__ void pair_absorb(uint32_t (&a)[25], const uint8_t* msg, uint64_t len,
+                                            int var, uint32_t h, uint32_t hi) {
+  namespace pr = kb::pair;
+  using S = SpongeShape<V>;
+#pragma unroll
+  for (int i = 0; i < 25; ++i) a[i] = 0u;
+  const int R = rate_of<V>(var);
+  const uint32_t sh = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(msg) & 3u);
+  const uint64_t nb = len / static_cast<uint64_t>(R) + 1u;
+  pr::HalfDw<V> d;
+  pr::load_halves<V>(d, msg, sh, len, 0, R, h);
+  for (uint64_t b = 0; b < nb; ++b) {
+    const uint64_t boff = b * static_cast<uint64_t>(R);
+    const bool fin = b + 1 == nb;
+    pr::absorb_halves<V>(a, d, sh, R, fin, fin ? static_cast<uint32_t>(len - boff) : 0u, S::kPadByte, h);
+    if (!fin) pr::load_halves<V>(d, msg, sh, len, boff + R, R, h);
+    pr::pair_permute(a, hi);
+  }
+}
+
+// XOF squeeze in the pair form: each lane writes its halves of the words in
+// the rate, r bits per permutation, until out_len bytes are out.
+template <int V>
+__device__ __forceinline__ void pair_xof(uint32_t (&a)[25], uint8_t* out, uint64_t out_len,
+                                         uint32_t h, uint32_t hi) {
+  constexpr uint32_t R = SpongeShape<V>::kMaxRate;
+  const bool words = (out_len & 3u) == 0 && (reinterpret_cast<uintptr_t>(out) & 3u) == 0;
+  for (uint64_t done = 0;;) {
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(R / 8); ++i) {
+      const uint64_t at = done + 8u * i + 4u * h;
+      if (at < out_len) {
+        if (words) {
+          *reinterpret_cast<uint32_t*>(out + at) = a[i];
+        } else {
+          for (uint32_t q = 0; q < 4u && at + q < out_len; ++q)
+            out[at + q] = static_cast<uint8_t>(a[i] >> (8u * q));
+        }
+      }
+    }
+    done += R;
+    if (done >= out_len) break;
+    kb::pair::pair_permute(a, hi);
+  }
+}
+
+// Pair form: each pair of lanes hashes one message at a time, message
+// order[first + p] (or first + p) for p = state, state + states, ...  One
+// wave per workgroup, as in the other lane-split forms.
+constexpr int kPairBlock = 64;
+constexpr int kPairStates = kPairBlock / kb::pair::kPairLanes;
+
+template <int V>
+__global__ __launch_bounds__(kPairBlock) void k_pair(const uint8_t* __restrict__ data,
+                                                     const uint64_t* __restrict__ offs,
+                                                     const uint64_t* __restrict__ lens,
+                                                     const uint8_t* __restrict__ vars,
+                                                     const uint32_t* __restrict__ order,
+                                                     uint64_t first, uint64_t count,
+                                                     uint8_t* __restrict__ out, uint64_t stride) {
+  namespace pr = kb::pair;
+  const uint32_t st = threadIdx.x / pr::kPairLanes, h = threadIdx.x % pr::kPairLanes;
+  const uint32_t hi = h ? ~0u : 0u;
+  const uint64_t states = static_cast<uint64_t>(gridDim.x) * kPairStates;
+  const int slot_dw = V == kMixed ? 16 : V >= kShake128 ? 0 : kb::digest_bytes_of(V) / 4;
+  for (uint64_t p = static_cast<uint64_t>(blockIdx.x) * kPairStates + st; p < count; p += states) {
+    const uint64_t i = order ? order[first + p] : first + p;
+    uint32_t a[25];
+    if constexpr (V >= kShake128) {
+      pair_absorb<V>(a, data + offs[i], lens[i], V, h, hi);
+      pair_xof<V>(a, out + i * stride, stride, h, hi);
+      continue;
+    }
+    const int var = V == kMixed ? vars[i] : V;
+    uint32_t* o = reinterpret_cast<uint32_t*>(out + i * stride);
+    if (V == kMixed && var > 3) {  // no such variant: the slot is zeroed
+#pragma unroll
+      for (int k = 0; k < 25; ++k) a[k] = 0u;
+      pr::store_halves(o, a, 0, slot_dw, h);
+      continue;
+    }
+    pair_absorb<V>(a, data + offs[i], lens[i], var, h, hi);
+    const int dw = V == kMixed ? kb::digest_bytes_rt(var) / 4 : kb::digest_bytes_of(V) / 4;
+    pr::store_halves(o, a, dw, slot_dw, h);
   }
 }
 
@@ -1511,6 +1603,26 @@ int launch_wide(const Batch& b, const uint32_t* order, uint64_t first, uint64_t 
   return KB_OK;
 }
 
+template <int V>
+int launch_pair(const Batch& b, const uint32_t* order, uint64_t first, uint64_t count,
+                hipStream_t s) {
+  if (!count) return KB_OK;
+  int dev = 0, cus = 0;
+  KB_HIP(hipGetDevice(&dev));
+  int rc = cu_count(dev, &cus);
+  if (rc) return rc;
+  // one state per message up to 16 waves per CU; beyond that states loop
+  uint64_t grid = (count + kPairStates - 1) / kPairStates;
+  if (grid > static_cast<uint64_t>(16 * cus)) grid = 16 * cus;
+  {
+    TimedLaunch tl(s, KB_KERNEL_PAIR);
+    hipLaunchKernelGGL(k_pair<V>, dim3(static_cast<uint32_t>(grid)), dim3(kPairBlock), 0, s,
+                       b.data, b.offs, b.lens, b.vars, order, first, count, b.out, b.stride);
+  }
+  KB_HIP(hipGetLastError());
+  return KB_OK;
+}
+
 // Workgroups of `kernel` that fit on the chip at once, capped by the tile's
 // waves per SIMD (a 256-thread workgroup is one wave on each of a CU's four
 // SIMDs).
@@ -1639,6 +1751,7 @@ int run_batch(const Batch& b, int mode, const kb_tile* tile, hipStream_t s, Work
   if (mode == KB_MODE_PLAIN) return launch_plain<V>(b, nullptr, 0, b.n, s);
   if (mode == KB_MODE_SPLIT) return launch_split<V>(b, nullptr, 0, b.n, s);
   if (mode == KB_MODE_WIDE) return launch_wide<V>(b, nullptr, 0, b.n, s);
+  if (mode == KB_MODE_PAIR) return launch_pair<V>(b, nullptr, 0, b.n, s);
   if (b.n >= 0xFFFFFFFFull) return launch_plain<V>(b, nullptr, 0, b.n, s);  // 32-bit order[]
   Workspace* w = own;
   int rc = own ? KB_OK : get_ws(s, b.n, 0, &w);
@@ -1664,7 +1777,7 @@ int check_batch(const Batch& b, int mode) {
   if (b.variant != kMixed && b.variant != kShake128 && b.variant != kShake256 &&
       (b.variant < 0 || b.variant > 3))
     return fail(KB_EINVAL, "variant %d is not a SHA-3 variant (0..3)", b.variant);
-  if (mode < KB_MODE_PERSISTENT || mode > KB_MODE_WIDE)
+  if (mode < KB_MODE_PERSISTENT || mode > KB_MODE_PAIR)
     return fail(KB_EINVAL, "unknown scheduling mode %d", mode);
   if (b.n == 0) return KB_OK;
   if (!b.data || !b.offs || !b.lens || !b.out || (b.variant == kMixed && !b.vars))
@@ -2365,7 +2478,7 @@ int keccak_timing_read(double* total_ms, uint64_t* launches) {
 }
 
 int keccak_timing_read_kernel(int kind, double* total_ms, uint64_t* launches) {
-  if (kind < KB_KERNEL_FIRST_PASS || kind > KB_KERNEL_SCHEDULE) {
+  if (kind < KB_KERNEL_FIRST_PASS || kind > KB_KERNEL_PAIR) {
     g_err.clear();
     return fail(KB_EINVAL, "unknown kernel kind %d", kind);
   }

@@ -22,7 +22,7 @@ DIGEST_BYTES = (28, 32, 48, 64)
 RATE_BYTES = (144, 136, 104, 72)
 
 MODE_PERSISTENT, MODE_PLAIN, MODE_PER_BUCKET, MODE_SPLIT = 0, 1, 2, 3
-MODES = {"persistent": 0, "plain": 1, "per_bucket": 2, "split": 3, "wide": 4}
+MODES = {"persistent": 0, "plain": 1, "per_bucket": 2, "split": 3, "wide": 4, "pair": 5}
 
 KB_OK, KB_EINVAL, KB_ENOMEM, KB_EHIP = 0, -1, -2, -3
 NOALLOC_MAX_MSGS = 1 << 20
@@ -643,7 +643,7 @@ def timing_enable(on: bool = True):
 
 
 KERNELS = {"first_pass": 0, "second_pass": 1, "plain": 2, "split": 3, "tree": 4, "wide": 5,
-           "schedule": 6}
+           "schedule": 6, "pair": 7}
 
 
 def timing_read(kernel: str | None = None) -> tuple[float, int]:

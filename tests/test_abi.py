@@ -76,10 +76,11 @@ def test_argument_errors_need_no_device(lib):
     t.class_threads[3] = 5
     assert lib.keccak_batch_ex(1, None, p, p, p, 4, p, 0, ctypes.byref(t), None) == kb.KB_EINVAL
     assert b"class_threads[3]" in lib.keccak_last_error()
-    # the wide mode is a known mode (the null device pointers fail later, on
-    # the device, so only the mode check is exercised here through n == 0)
+    # the wide and pair modes are known modes (only the mode check is
+    # exercised here, through n == 0)
     assert lib.keccak_batch_ex(1, None, None, None, None, 0, None, 4, None, None) == kb.KB_OK
-    assert lib.keccak_batch_ex(1, None, None, None, None, 0, None, 5, None, None) == kb.KB_EINVAL
+    assert lib.keccak_batch_ex(1, None, None, None, None, 0, None, 5, None, None) == kb.KB_OK
+    assert lib.keccak_batch_ex(1, None, None, None, None, 0, None, 6, None, None) == kb.KB_EINVAL
     # tree mode
     assert lib.merkle_root(1, p, 100, 0, p, None) == kb.KB_EINVAL
     assert lib.merkle_root(5, p, 100, 10, p, None) == kb.KB_EINVAL

@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 RATES = (144, 136, 104, 72)
 DIGEST = (28, 32, 48, 64)
-MODES = ("persistent", "plain", "per_bucket", "split", "wide")
+MODES = ("persistent", "plain", "per_bucket", "split", "wide", "pair")
 
 
 @pytest.fixture(scope="module")
@@ -141,7 +141,7 @@ def test_persistent_split_tail(kb, o2, case):
     assert (got1 == o2.sha3_batch(256, v1.data, v1.offsets, v1.lengths)).all()
 
 
-@pytest.mark.parametrize("mode", ["persistent", "split", "wide"])
+@pytest.mark.parametrize("mode", ["persistent", "split", "wide", "pair"])
 def test_mixed_invalid_variant_slot_is_zero(kb, o2, mode):
     b = wl.explicit([10, 200, 0, 77], seed=5, variant=np.array([1, 9, 3, 255], dtype=np.uint8))
     _say("mixed invalid variant", mode)
@@ -151,7 +151,7 @@ def test_mixed_invalid_variant_slot_is_zero(kb, o2, mode):
     assert (got[0] == want[0]).all() and (got[2] == want[2]).all()
 
 
-@pytest.mark.parametrize("mode", ["persistent", "split", "wide"])
+@pytest.mark.parametrize("mode", ["persistent", "split", "wide", "pair"])
 def test_edge_cases(kb, o2, mode):
     import torch
     _say("edge: empty batch", mode)
@@ -352,7 +352,7 @@ def test_full_merkle_1gib(kb, o2):
 
 
 @pytest.mark.parametrize("security", [128, 256])
-@pytest.mark.parametrize("mode", ["persistent", "plain", "split", "wide"])
+@pytest.mark.parametrize("mode", ["persistent", "plain", "split", "wide", "pair"])
 def test_shake_xof(kb, o2, security, mode):
     import torch
     R = 168 if security == 128 else 136

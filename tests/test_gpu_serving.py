@@ -154,7 +154,7 @@ def test_cached_tile_is_chosen_and_matches_oracle(kb, o2, tmp_path, monkeypatch)
     assert not cached and used.waves_per_simd == 0
 
 
-@pytest.mark.parametrize("mode", ["persistent", "plain", "split", "wide"])
+@pytest.mark.parametrize("mode", ["persistent", "plain", "split", "wide", "pair"])
 def test_graph_replays_equal_eager(kb, mode):
     import torch
     b = wl.uneven(20000, 5000, seed=53)
