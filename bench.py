@@ -429,7 +429,7 @@ def main():
                          "64 B, plain launch against the CPU oracle; uneven: 2^20 "
                          "mixed-variant messages, log-uniform lengths in [0, 16 KiB]; merkle: "
                          "1 GiB in 4 KiB leaves; serving: Poisson request stream; latency: "
-                         "1 to 32768 long messages, one thread vs five or 32 lanes per message")
+                         "1 to 32768 long messages, one thread vs two, five or 32 lanes per message")
     args = ap.parse_args()
 
     if args.gpus != 1:
