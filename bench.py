@@ -3,8 +3,9 @@
 
 One step = one keccak_batch call over the whole resident batch (the full
 hot path: block counts, bucketing decision, scheduling and the persistent
-hashing kernel).  W untimed warmup steps, then exactly K timed steps between
-two device synchronisations.  Prints one JSON line with Mhash/s, GB/s hashed,
+hashing kernel).  After 0.2 s of untimed steps that let the shader clock
+settle, W untimed warmup steps, then exactly K timed steps between two device
+synchronisations.  Prints one JSON line with Mhash/s, GB/s hashed,
 the plain one-launch and one-launch-per-bucket forms on the same inputs (each
 timed after its own warmup, then the persistent and plain forms alternately),
 the roofline of the dominant kernel (timed live with HIP events on its launch
@@ -123,19 +124,43 @@ def cpu_baseline(batch, extra: bool = True):
     return rep, want
 
 
-def time_steps(torch, fn, steps, warmup, on_timed=None):
-    """Mean wall time of `steps` calls after `warmup` untimed ones; `on_timed`
-    runs between the two (to arm the kernel timing hooks for the timed steps)."""
+# Untimed work before the warmup steps: the shader clock takes some tens of
+# milliseconds of load to settle (the first 20 steps of the 2^24 x 64 B batch
+# after five warmup steps ran about 2 % slower than later ones).
+SETTLE_S = 0.2
+
+
+def settle(torch, fn, seconds=SETTLE_S):
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end:
+        fn()
+        torch.cuda.synchronize()
+
+
+def time_steps(torch, kbatch, fn, steps, warmup, kernel_times=True):
+    """(mean wall seconds, kernel milliseconds, bracketed launches) of `steps`
+    calls after the clock has settled and `warmup` untimed calls.  The wall
+    time is taken with the library's event brackets off (each bracket adds
+    stream time); the kernel time comes from `steps` further calls with
+    every launch bracketed (zero without `kernel_times`)."""
+    settle(torch, fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    if on_timed:
-        on_timed()
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    wall = (time.perf_counter() - t0) / steps
+    if not kernel_times:
+        return wall, 0.0, 0
+    kbatch.timing_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    k_ms, k_n = kbatch.timing_read()
+    kbatch.timing_enable(False)
+    return wall, k_ms, k_n
 
 
 def bench_uneven(args, kbatch, workloads, torch, dev):
@@ -154,9 +179,7 @@ def bench_uneven(args, kbatch, workloads, torch, dev):
     for mode in ("persistent", "plain", "per_bucket"):
         fn = lambda: kbatch.keccak_batch_mixed(var, data, offs, lens, out=out, mode=mode,
                                                check_bounds=False)
-        t = time_steps(torch, fn, args.steps, args.warmup, lambda: kbatch.timing_enable(True))
-        k_ms, k_n = kbatch.timing_read()
-        kbatch.timing_enable(False)
+        t, k_ms, k_n = time_steps(torch, kbatch, fn, args.steps, args.warmup)
         steps_timed = args.steps
         res[mode] = {"ms_per_step": round(t * 1e3, 4), "mhash_s": round(b.n / t / 1e6, 2),
                      "gb_per_s_hashed": round(b.total_bytes / t / 1e9, 2),
@@ -188,9 +211,7 @@ def bench_small(args, kbatch, workloads, torch, dev):
         out = torch.empty((n, 32), dtype=torch.uint8, device=dev)
         fn = lambda: kbatch.keccak_batch(VARIANT, data, offs, lens, out=out, mode=mode,
                                          check_bounds=False)
-        t = time_steps(torch, fn, args.steps, args.warmup, lambda: kbatch.timing_enable(True))
-        k_ms, k_n = kbatch.timing_read()
-        kbatch.timing_enable(False)
+        t, k_ms, k_n = time_steps(torch, kbatch, fn, args.steps, args.warmup)
         # wall time per call includes the Python binding's per-call work;
         # the kernels' own time (HIP events around each launch) does not
         res[mode] = {"us_per_batch": round(t * 1e6, 2), "mhash_s": round(n / t / 1e6, 2),
@@ -215,10 +236,8 @@ def bench_merkle(args, kbatch, workloads, torch, dev):
     leaves = total // 4096
     perms = leaves * (4096 // 136 + 1) + (leaves - 1)
     kbatch.reserve(0, leaves)
-    t = time_steps(torch, lambda: kbatch.merkle_root(1, data, 4096, out=root), args.steps,
-                   args.warmup, lambda: kbatch.timing_enable(True))
-    k_ms, k_n = kbatch.timing_read()
-    kbatch.timing_enable(False)
+    t, k_ms, k_n = time_steps(torch, kbatch, lambda: kbatch.merkle_root(1, data, 4096, out=root),
+                              args.steps, args.warmup)
     steps_timed = args.steps
     print(json.dumps({"config": {"workload": "merkle_1GiB_4KiB_leaves_sha3_256", "seed": 5,
                                  "leaves": leaves, "permutations": perms},
@@ -247,7 +266,7 @@ def bench_latency(args, kbatch, workloads, torch, dev):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch(1, data, offs, lens, out=out, mode=mode,
                                              check_bounds=False)
-            t = time_steps(torch, fn, args.steps, args.warmup)
+            t = time_steps(torch, kbatch, fn, args.steps, args.warmup, kernel_times=False)[0]
             row[mode] = {"ms": round(t * 1e3, 4), "us_per_block": round(t * 1e6 / nb, 3)}
             ref = out.clone() if ref is None else ref
             row[mode]["same_digests"] = bool(torch.equal(out, ref))
@@ -268,7 +287,7 @@ def bench_latency(args, kbatch, workloads, torch, dev):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch_xof(256, data, offs, lens, 32, out=out, mode=mode,
                                                  check_bounds=False)
-            t = time_steps(torch, fn, args.steps, args.warmup)
+            t = time_steps(torch, kbatch, fn, args.steps, args.warmup, kernel_times=False)[0]
             row[mode] = {"ms": round(t * 1e3, 4), "us_per_block": round(t * 1e6 / nb, 3)}
             ref = out.clone() if ref is None else ref
             row[mode]["same_output"] = bool(torch.equal(out, ref))
@@ -478,27 +497,28 @@ def main():
 
     # the roofline's two ceilings (the VALU issue rate with the shader clock,
     # and the bare permutation on register-held states with no memory
-    # traffic) run once before the warmup, which brings the chip's clock up,
-    # and are measured after the timed steps
+    # traffic) run once before the warmup and are measured after the timed
+    # steps
     kbatch.probe_valu()
     kbatch.probe_perm()
 
+    settle(torch, step)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    kbatch.timing_enable(True)
+    # the dominant kernel (the first pass hashes every chunk of this batch)
+    # is the only one bracketed by events in the timed steps: each bracket
+    # adds a few microseconds of stream time
+    kbatch.timing_enable(True, kinds=["first_pass"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # the dominant kernel: the first pass hashes every chunk of this batch
     k_ms, k_launches = kbatch.timing_read("first_pass")
-    k2_ms, k2_launches = kbatch.timing_read("second_pass")
-    ks_ms, ks_launches = kbatch.timing_read("schedule")
     kbatch.timing_enable(False)
     ms_per_step = 1e3 * wall / args.steps
     mhash = N_MSGS * args.steps / wall / 1e6
@@ -542,6 +562,15 @@ def main():
         print(f"[bench] alternating ms/step: {alternating}", file=sys.stderr, flush=True)
     else:
         alternating = None
+
+    # the scheduling and second-pass launches, bracketed in steps of their own
+    kbatch.timing_enable(True, kinds=["schedule", "second_pass"])
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    k2_ms, k2_launches = kbatch.timing_read("second_pass")
+    ks_ms, ks_launches = kbatch.timing_read("schedule")
+    kbatch.timing_enable(False)
 
     probe_tops, probe_mhz = kbatch.probe_valu()
     perm_gps, perm_waves = kbatch.probe_perm()

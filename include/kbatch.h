@@ -387,6 +387,14 @@ int keccak_release(void);
  * bracketed. */
 int keccak_timing_enable(int on);
 
+/* keccak_timing_enable restricted to the kernel kinds (enum kb_kernel) whose
+ * bit, 1 << kind, is set in `kinds`; 0 disables timing, and enabling clears
+ * the record.  Every bracket adds two event records to the launch stream,
+ * each a few microseconds of stream time, so a caller that times one kind
+ * of kernel inside a timed region brackets only that kind.  KB_EINVAL for a
+ * bit above KB_KERNEL_PAIR. */
+int keccak_timing_enable_kinds(uint32_t kinds);
+
 /* Sum of the bracketed kernel durations in milliseconds and the number of
  * bracketed launches since timing was enabled; waits for those events. */
 int keccak_timing_read(double* total_ms, uint64_t* launches);

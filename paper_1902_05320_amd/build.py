@@ -23,9 +23,6 @@ ARCH = "gfx950"
 SOURCES = [os.path.join(CSRC, "kbatch.hip"), os.path.join(CSRC, "probes.hip"),
            os.path.join(CSRC, "keccak_p.hip"),
            os.path.join(CSRC, "server.cpp"), os.path.join(CSRC, "tune_cache.cpp")]
-HEADERS = [os.path.join(CSRC, f) for f in ("keccak_device.h", "sponge_device.h", "split_device.h",
-                                         "kb_internal.h")] + [
-    os.path.join(INCLUDE, "kbatch.h")]
 
 
 def hipcc() -> str:

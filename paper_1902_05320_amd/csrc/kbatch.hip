@@ -1406,7 +1406,7 @@ struct Workspace {
 // Measurement hook state (keccak_timing_*): event pairs around kernel
 // launches, each tagged with the kind of kernel it brackets.
 struct Timing {
-  bool on = false;
+  uint32_t kinds = 0;  // bit k set: launches of kernel kind k are bracketed
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   std::vector<int> kind;
   size_t used = 0;
@@ -1420,7 +1420,7 @@ struct TimedLaunch {
   hipStream_t s;
   TimedLaunch(hipStream_t st, int kind) : s(st) {
     std::lock_guard<std::mutex> lk(g_tmu);
-    if (!g_timing.on) return;
+    if (kind < 0 || kind > 31 || !((g_timing.kinds >> kind) & 1u)) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     if (g_timing.used == g_timing.pool.size()) {
@@ -2444,12 +2444,17 @@ int keccak_release(void) {
   return rc;
 }
 
-int keccak_timing_enable(int on) {
+int keccak_timing_enable_kinds(uint32_t kinds) {
   g_err.clear();
+  if (kinds >> (KB_KERNEL_PAIR + 1)) return fail(KB_EINVAL, "unknown kernel kind in mask 0x%x", kinds);
   std::lock_guard<std::mutex> lk(g_tmu);
-  g_timing.on = on != 0;
+  g_timing.kinds = kinds;
   g_timing.used = 0;
   return KB_OK;
+}
+
+int keccak_timing_enable(int on) {
+  return keccak_timing_enable_kinds(on ? (2u << KB_KERNEL_PAIR) - 1u : 0u);
 }
 
 // Sum of the bracketed durations of kernels of kind `kind` (-1: every kind).

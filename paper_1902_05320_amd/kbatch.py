@@ -36,7 +36,8 @@ EXPORTS = (
     "keccak_server_result", "keccak_server_stats", "keccak_server_destroy",
     "keccak_server_last_error", "keccak_tree_workspace_bytes", "keccak_digest_bytes",
     "keccak_rate_bytes", "keccak_reserve", "keccak_release", "keccak_timing_enable",
-    "keccak_timing_read", "keccak_timing_read_kernel", "keccak_probe_valu", "keccak_probe_perm",
+    "keccak_timing_enable_kinds", "keccak_timing_read", "keccak_timing_read_kernel",
+    "keccak_probe_valu", "keccak_probe_perm",
     "keccak_probe_copy", "keccak_last_error", "keccak_version", "keccak_p_batch",
 )
 
@@ -117,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     lib.keccak_reserve.argtypes = [u64, u64, vp]
     lib.keccak_release.argtypes = []
     lib.keccak_timing_enable.argtypes = [i32]
+    lib.keccak_timing_enable_kinds.argtypes = [ctypes.c_uint32]
     lib.keccak_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_uint64)]
     lib.keccak_timing_read_kernel.argtypes = [i32, ctypes.POINTER(ctypes.c_double),
@@ -156,7 +158,8 @@ def load_library(path: str = LIB_PATH):
               "keccak_batch_ex",
               "merkle_root",
               "keccak_digest_bytes", "keccak_rate_bytes", "keccak_reserve", "keccak_release",
-              "keccak_timing_enable", "keccak_timing_read", "keccak_timing_read_kernel",
+              "keccak_timing_enable", "keccak_timing_enable_kinds", "keccak_timing_read",
+              "keccak_timing_read_kernel",
               "keccak_probe_valu",
               "keccak_probe_perm", "keccak_probe_copy", "keccak_autotune",
               "keccak_tune_store", "keccak_tune_lookup", "keccak_last_tile", "keccak_graph_create",
@@ -637,13 +640,21 @@ def release():
     _check(load_library().keccak_release())
 
 
-def timing_enable(on: bool = True):
-    """Bracket every hashing-kernel launch with HIP events on its stream."""
-    _check(load_library().keccak_timing_enable(1 if on else 0))
-
-
 KERNELS = {"first_pass": 0, "second_pass": 1, "plain": 2, "split": 3, "tree": 4, "wide": 5,
            "schedule": 6, "pair": 7}
+
+
+def timing_enable(on: bool = True, kinds=None):
+    """Bracket hashing-kernel launches with HIP events on their stream: every
+    kind, or only the kinds named in `kinds` (keys of KERNELS)."""
+    lib = load_library()
+    if kinds is None:
+        _check(lib.keccak_timing_enable(1 if on else 0))
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << KERNELS[k]
+        _check(lib.keccak_timing_enable_kinds(mask if on else 0))
 
 
 def timing_read(kernel: str | None = None) -> tuple[float, int]:

@@ -108,6 +108,18 @@ def test_probe_argument_errors_need_no_device(lib):
     assert lib.keccak_probe_perm(10, 0, ctypes.byref(g), None, None) == kb.KB_EINVAL
 
 
+def test_timing_kinds_need_no_device(lib):
+    from paper_1902_05320_amd import kbatch as kb
+    ms, cnt = ctypes.c_double(1.0), ctypes.c_uint64(1)
+    assert lib.keccak_timing_enable_kinds(1 << (max(kb.KERNELS.values()) + 1)) == kb.KB_EINVAL
+    assert b"kind" in lib.keccak_last_error()
+    assert lib.keccak_timing_enable_kinds(1 << kb.KERNELS["first_pass"]) == kb.KB_OK
+    assert lib.keccak_timing_read(ctypes.byref(ms), ctypes.byref(cnt)) == kb.KB_OK
+    assert (ms.value, cnt.value) == (0.0, 0)
+    assert lib.keccak_timing_enable(1) == kb.KB_OK and lib.keccak_timing_enable(0) == kb.KB_OK
+    assert lib.keccak_timing_enable_kinds(0) == kb.KB_OK
+
+
 def test_xof_ex_argument_errors_need_no_device(lib):
     from paper_1902_05320_amd import kbatch as kb
     p = ctypes.c_void_p(0x1000)

@@ -209,6 +209,29 @@ def test_order_and_repeat_invariance(kb):
     assert torch.equal(p, a[perm])
 
 
+def test_timing_brackets_only_the_selected_kinds(kb, o2):
+    import torch
+    b = wl.uneven(3000, 3000, seed=13)
+    data, offs, lens, _ = _to_dev(b)
+    _say("timing kinds: first pass only, then every kind")
+    kb.timing_enable(True, kinds=["first_pass"])
+    for _ in range(3):
+        out = kb.keccak_batch(1, data, offs, lens)
+    torch.cuda.synchronize()
+    ms, n = kb.timing_read()
+    assert n == 3 and ms > 0.0
+    assert kb.timing_read("first_pass")[1] == 3
+    assert kb.timing_read("schedule") == (0.0, 0) and kb.timing_read("second_pass") == (0.0, 0)
+    kb.timing_enable(True)
+    out = kb.keccak_batch(1, data, offs, lens)
+    torch.cuda.synchronize()
+    assert kb.timing_read("first_pass")[1] == 1 and kb.timing_read("second_pass")[1] == 1
+    assert kb.timing_read("schedule")[1] == 2
+    kb.timing_enable(False)
+    want = o2.sha3_batch(256, b.data, b.offsets, b.lengths)
+    assert _mismatches(out.cpu().numpy(), want)[1] == 0
+
+
 @pytest.mark.parametrize("v", [0, 1, 2, 3])
 def test_merkle_small_trees(kb, o2, v):
     import torch
