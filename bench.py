@@ -124,26 +124,27 @@ def cpu_baseline(batch, extra: bool = True):
     return rep, want
 
 
-# Untimed work before the warmup steps: the shader clock takes some tens of
-# milliseconds of load to settle (the first 20 steps of the 2^24 x 64 B batch
-# after five warmup steps ran about 2 % slower than later ones).
+# Untimed work before the warmup steps (--settle-s): the shader clock takes
+# some tens of milliseconds of load to settle (the first 20 steps of the
+# 2^24 x 64 B batch after five warmup steps ran about 2 % slower than later
+# ones).
 SETTLE_S = 0.2
 
 
-def settle(torch, fn, seconds=SETTLE_S):
+def settle(torch, fn, seconds):
     t_end = time.perf_counter() + seconds
     while time.perf_counter() < t_end:
         fn()
         torch.cuda.synchronize()
 
 
-def time_steps(torch, kbatch, fn, steps, warmup, kernel_times=True):
+def time_steps(torch, kbatch, fn, steps, warmup, kernel_times=True, settle_s=SETTLE_S):
     """(mean wall seconds, kernel milliseconds, bracketed launches) of `steps`
     calls after the clock has settled and `warmup` untimed calls.  The wall
     time is taken with the library's event brackets off (each bracket adds
     stream time); the kernel time comes from `steps` further calls with
     every launch bracketed (zero without `kernel_times`)."""
-    settle(torch, fn)
+    settle(torch, fn, settle_s)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -179,7 +180,8 @@ def bench_uneven(args, kbatch, workloads, torch, dev):
     for mode in ("persistent", "plain", "per_bucket"):
         fn = lambda: kbatch.keccak_batch_mixed(var, data, offs, lens, out=out, mode=mode,
                                                check_bounds=False)
-        t, k_ms, k_n = time_steps(torch, kbatch, fn, args.steps, args.warmup)
+        t, k_ms, k_n = time_steps(torch, kbatch, fn, args.steps, args.warmup,
+                                  settle_s=args.settle_s)
         steps_timed = args.steps
         res[mode] = {"ms_per_step": round(t * 1e3, 4), "mhash_s": round(b.n / t / 1e6, 2),
                      "gb_per_s_hashed": round(b.total_bytes / t / 1e9, 2),
@@ -211,7 +213,8 @@ def bench_small(args, kbatch, workloads, torch, dev):
         out = torch.empty((n, 32), dtype=torch.uint8, device=dev)
         fn = lambda: kbatch.keccak_batch(VARIANT, data, offs, lens, out=out, mode=mode,
                                          check_bounds=False)
-        t, k_ms, k_n = time_steps(torch, kbatch, fn, args.steps, args.warmup)
+        t, k_ms, k_n = time_steps(torch, kbatch, fn, args.steps, args.warmup,
+                                  settle_s=args.settle_s)
         # wall time per call includes the Python binding's per-call work;
         # the kernels' own time (HIP events around each launch) does not
         res[mode] = {"us_per_batch": round(t * 1e6, 2), "mhash_s": round(n / t / 1e6, 2),
@@ -237,7 +240,7 @@ def bench_merkle(args, kbatch, workloads, torch, dev):
     perms = leaves * (4096 // 136 + 1) + (leaves - 1)
     kbatch.reserve(0, leaves)
     t, k_ms, k_n = time_steps(torch, kbatch, lambda: kbatch.merkle_root(1, data, 4096, out=root),
-                              args.steps, args.warmup)
+                              args.steps, args.warmup, settle_s=args.settle_s)
     steps_timed = args.steps
     print(json.dumps({"config": {"workload": "merkle_1GiB_4KiB_leaves_sha3_256", "seed": 5,
                                  "leaves": leaves, "permutations": perms},
@@ -266,7 +269,8 @@ def bench_latency(args, kbatch, workloads, torch, dev):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch(1, data, offs, lens, out=out, mode=mode,
                                              check_bounds=False)
-            t = time_steps(torch, kbatch, fn, args.steps, args.warmup, kernel_times=False)[0]
+            t = time_steps(torch, kbatch, fn, args.steps, args.warmup, kernel_times=False,
+                           settle_s=args.settle_s)[0]
             row[mode] = {"ms": round(t * 1e3, 4), "us_per_block": round(t * 1e6 / nb, 3)}
             ref = out.clone() if ref is None else ref
             row[mode]["same_digests"] = bool(torch.equal(out, ref))
@@ -287,7 +291,8 @@ def bench_latency(args, kbatch, workloads, torch, dev):
             out = torch.empty((k, 32), dtype=torch.uint8, device=dev)
             fn = lambda: kbatch.keccak_batch_xof(256, data, offs, lens, 32, out=out, mode=mode,
                                                  check_bounds=False)
-            t = time_steps(torch, kbatch, fn, args.steps, args.warmup, kernel_times=False)[0]
+            t = time_steps(torch, kbatch, fn, args.steps, args.warmup, kernel_times=False,
+                           settle_s=args.settle_s)[0]
             row[mode] = {"ms": round(t * 1e3, 4), "us_per_block": round(t * 1e6 / nb, 3)}
             ref = out.clone() if ref is None else ref
             row[mode]["same_output"] = bool(torch.equal(out, ref))
@@ -428,6 +433,8 @@ def main():
     # the GPU's clock ramps over the first dozen or so 2-ms steps of a fresh
     # process (kernel time falls from ~2.0 to ~1.7 ms); warm up past that
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--settle-s", type=float, default=SETTLE_S,
+                    help="seconds of untimed steps before the warmup (shader clock settling)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the single-core and hashlib timings (the whole-batch oracle "
                          "run always happens: it is the bit-exact check)")
@@ -502,7 +509,7 @@ def main():
     kbatch.probe_valu()
     kbatch.probe_perm()
 
-    settle(torch, step)
+    settle(torch, step, args.settle_s)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
