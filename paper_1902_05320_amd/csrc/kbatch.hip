@@ -842,7 +842,8 @@ constexpr uint32_t kRanksPerThread = kKeyBins / kBlock;
 // The first CTL_SPLIT_N positions of the bucketed order (the longest
 // messages) go to the split form: the messages of at least
 // max(kSplitMinKey, 2 x the blocks per resident lane) blocks, at most
-// `split_cap` of them.  Below the second bound the batch's throughput, not
+// `split_cap` of them (twice that when every deferred message qualifies).
+// Below the second bound the batch's throughput, not
 // its longest chain, sets the time, and a split item (two messages per wave)
 // costs throughput.  (An earlier bound of 4 x the mean block count kept a
 // batch of a few equal long messages out of the split form: 8 x 64 KiB ran
@@ -973,7 +974,13 @@ __device__ void make_plan(const PassArgs& a, uint32_t* scratch) {
   }
   __syncthreads();
   const uint32_t split_all = __builtin_amdgcn_readfirstlane(s_split);
-  const uint32_t split = split_all < a.split_cap ? split_all : a.split_cap;
+  // When every deferred message is a split candidate and there are at most
+  // twice the cap, the front waves take them all in two rounds: the excess
+  // would otherwise run one lane per message, a chain at about a third of
+  // the wide form's speed.
+  const uint32_t cap =
+      split_all == ndef && ndef <= 2u * a.split_cap ? 2u * a.split_cap : a.split_cap;
+  const uint32_t split = split_all < cap ? split_all : cap;
   // queue items over the positions past the split range
   uint32_t items[kRanksPerThread], it_sum = 0;
 #pragma unroll
@@ -1256,6 +1263,13 @@ __global__ __launch_bounds__(kBlock) void k_second(PassArgs a) {
     // runs about three times as fast as one thread's.  The exchange areas are
     // this wave's own staging rows.  The XOFs squeeze in the same form.
     const uint32_t split_n = ctl[CTL_SPLIT_N];
+    // With no split tail and no more queue items than SIMDs, the front waves
+    // (one per SIMD) take every item: a second wave on a SIMD would share its
+    // issue slots and stretch both items' chains while other SIMDs idle.  The
+    // mixed-variant kernel keeps every wave claiming: in it this test alone
+    // moved the hashing code and cost the uneven batch a tenth.
+    if constexpr (V != kMixed)
+      if (!front && split_n == 0u && n_items <= a.split_cap / (kSplitItemsPerSimd * kWideStates)) return;
     {
       if (front && split_n) {
         namespace wd = kb::wide;

@@ -117,18 +117,26 @@ def test_count_pass_boundaries(kb, o2):
             assert (got1 == o2.sha3_batch(256, b.data, b.offsets, b.lengths)).all(), (n, equal)
 
 
-@pytest.mark.parametrize("case", ["few_long", "many_long"])
+@pytest.mark.parametrize("case", ["few_long", "many_long", "all_long", "few_items"])
 def test_persistent_split_tail(kb, o2, case):
-    # the longest messages of a bucketed batch go to the split form (at
-    # most eight per SIMD, and only messages of at least 4x the mean block
-    # count); few: 40 messages of ~0.2-1 MB among 60000 short ones; many:
-    # 12000 messages of ~20 KB among 200000 short ones, more than the split
-    # cap, so the rest of their buckets runs one message per thread
+    # the longest messages of a bucketed batch go to the wide split tail (at
+    # most two per SIMD, and only messages of at least max(32, 2 x blocks
+    # per resident lane) blocks); few: 40 messages of ~0.2-1 MB among 60000
+    # short ones; many: 12000 messages of ~20 KB among 200000 short ones,
+    # more than the split cap, so the rest of their buckets runs one message
+    # per thread; all: 3000 messages of ~16 KB and nothing shorter, between
+    # one and two caps, so all go to the tail in two rounds; few items:
+    # 5000 messages of 1-3 KB (under 32 blocks), fewer queue items than
+    # SIMDs and no tail, so only each SIMD's front wave takes items
     rng = np.random.Generator(np.random.PCG64(70))
     if case == "few_long":
         lens = np.concatenate([rng.integers(0, 300, 60000), rng.integers(200_000, 1_000_000, 40)])
-    else:
+    elif case == "many_long":
         lens = np.concatenate([rng.integers(0, 300, 200000), rng.integers(19_000, 21_000, 12000)])
+    elif case == "all_long":
+        lens = rng.integers(15_000, 17_000, 3000)
+    else:
+        lens = rng.integers(1_000, 3_000, 5000)
     rng.shuffle(lens)
     var = rng.integers(0, 4, lens.size).astype(np.uint8)
     b = wl.explicit(lens, seed=71, variant=var, gap=1, lead=3)
