@@ -177,7 +177,7 @@ def bench_uneven(args, kbatch, workloads, torch, dev):
     rates = np.array([144, 136, 104, 72])[b.variants]
     perms = int((b.lengths // rates + 1).sum())
     res = {}
-    for mode in ("persistent", "plain", "per_bucket"):
+    for mode in ("persistent",) if args.no_plain else ("persistent", "plain", "per_bucket"):
         fn = lambda: kbatch.keccak_batch_mixed(var, data, offs, lens, out=out, mode=mode,
                                                check_bounds=False)
         t, k_ms, k_n = time_steps(torch, kbatch, fn, args.steps, args.warmup,
@@ -438,7 +438,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the single-core and hashlib timings (the whole-batch oracle "
                          "run always happens: it is the bit-exact check)")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form comparison")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain (and, for the uneven batch, per-bucket) comparisons")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the library's copy probe over MIB MiB (for counter scaling)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
